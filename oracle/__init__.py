@@ -1,0 +1,198 @@
+"""CPU oracle for the Fireflies particle-RK4 hot path (arXiv:1505.00344).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library ``paper_1505_00344_amd`` and neither imports the
+other.  Everything here is a thin numpy/ctypes wrapper around ``ffo.cpp``; see
+``ffo.h`` for what each function computes and which passage of the paper it
+follows.
+
+Arrays are structure-of-arrays: ``state`` has shape ``(dim, n)`` (component d
+of particle i is ``state[d, i]``), per-particle parameters have shape
+``(n_pp, n)`` and replace global parameter ``pp_slot[k]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffo.so")
+
+LINEAR, LORENZ, WILSON_COWAN, HH_RING, RICCATI = 0, 1, 2, 3, 100
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+
+def lib():
+    """Load libffo.so (building it first if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.ffo_n_params.argtypes = [_int, _int]
+        L.ffo_rhs.argtypes = [_int, _int, _dp, _int, _dp, _dp, _i64]
+        L.ffo_jacobians.argtypes = [_int, _int, _dp, _int, _dp, _dp, _dp, _i64]
+        L.ffo_rk4.argtypes = [_int, _int, _dp, _int, _ip, _int, _dp, _dp, _i64, _i64,
+                              ctypes.c_double, _i64, _int]
+        L.ffo_rk4_f32.argtypes = [_int, _int, _dp, _int, _ip, _int, _fp, _fp, _fp, _int,
+                                  _i64, _i64, ctypes.c_float, _i64, _int]
+        L.ffo_rk4_cstep.argtypes = [_int, _int, _dp, _int, _ip, _int, _dp, _dp, _dp, _dp,
+                                    _dp, ctypes.c_double, _dp, _dp, _i64, _i64,
+                                    ctypes.c_double, _i64, _int]
+        L.ffo_adjoint.argtypes = [_int, _int, _dp, _int, _ip, _int, _dp, _dp, _dp, _dp,
+                                  _dp, _i64, _i64, ctypes.c_double, _i64, _int]
+        L.ffo_histogram.argtypes = [_int, _dp, _int, _dp, _i64, _i64, _int, _int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, _int, _int, _u32p, _u64p, _int]
+        for f in ("ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32",
+                  "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram"):
+            getattr(L, f).restype = _int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, typ):
+    if a is None:
+        return ctypes.cast(None, typ)
+    return a.ctypes.data_as(typ)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what}: invalid arguments (code {rc})")
+
+
+def n_params(sys: int, dim: int) -> int:
+    return lib().ffo_n_params(sys, dim)
+
+
+def _pp(pp_slot, pparams, n, conv):
+    if pp_slot is None or len(pp_slot) == 0:
+        return None, 0, None
+    slots = np.ascontiguousarray(pp_slot, dtype=np.int32)
+    pp = conv(pparams).reshape(len(slots), n)
+    return slots, len(slots), pp
+
+
+def rhs(sys, params, x):
+    """f(x) at points x of shape (m, dim)."""
+    x = _f64(np.atleast_2d(x))
+    m, dim = x.shape
+    p = _f64(params)
+    f = np.empty_like(x)
+    _check(lib().ffo_rhs(sys, dim, _ptr(p, _dp), len(p), _ptr(x, _dp), _ptr(f, _dp), m), "rhs")
+    return f
+
+
+def jacobians(sys, params, x):
+    """(J, Fp) at points x of shape (m, dim): J (m, dim, dim), Fp (m, dim, n_params)."""
+    x = _f64(np.atleast_2d(x))
+    m, dim = x.shape
+    p = _f64(params)
+    J = np.empty((m, dim, dim))
+    Fp = np.empty((m, dim, max(len(p), 1)))
+    _check(lib().ffo_jacobians(sys, dim, _ptr(p, _dp), len(p), _ptr(x, _dp), _ptr(J, _dp),
+                               _ptr(Fp, _dp), m), "jacobians")
+    return J, Fp[:, :, :len(p)]
+
+
+def rk4(sys, params, state, h, nsteps, pp_slot=None, pparams=None, nthreads=0):
+    """FP64 classical RK4; returns the final state (a new (dim, n) array)."""
+    st = _f64(state).copy()
+    dim, n = st.shape
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64)
+    _check(lib().ffo_rk4(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp, _ptr(pp, _dp),
+                         _ptr(st, _dp), n, n, float(h), int(nsteps), nthreads), "rk4")
+    return st
+
+
+def rk4_f32(sys, params, state, h, nsteps, pp_slot=None, pparams=None, kahan=False,
+            comp=None, nthreads=0):
+    """Single-precision RK4 (params rounded to float); returns (state, comp)."""
+    st = _f32(state).copy()
+    dim, n = st.shape
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f32)
+    c = None
+    if kahan:
+        c = np.zeros_like(st) if comp is None else _f32(comp).copy()
+    _check(lib().ffo_rk4_f32(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                             _ptr(pp, _fp), _ptr(st, _fp), _ptr(c, _fp), int(bool(kahan)), n,
+                             n, float(np.float32(h)), int(nsteps), nthreads), "rk4_f32")
+    return st, c
+
+
+def rk4_cstep(sys, params, x0, h, nsteps, pp_slot=None, pparams=None, dx0=None,
+              dparams=None, dpp=None, eps=1e-30, nthreads=0):
+    """Complex-step directional derivative of the FP64 map: returns (xT, dxT)."""
+    x0 = _f64(x0)
+    dim, n = x0.shape
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64)
+    dx0 = None if dx0 is None else _f64(dx0).reshape(dim, n)
+    dparams = None if dparams is None else _f64(dparams)
+    dpp = None if dpp is None else _f64(dpp).reshape(npp, n)
+    xT = np.empty_like(x0)
+    dxT = np.empty_like(x0)
+    _check(lib().ffo_rk4_cstep(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                               _ptr(pp, _dp), _ptr(x0, _dp), _ptr(dx0, _dp), _ptr(dparams, _dp),
+                               _ptr(dpp, _dp), float(eps), _ptr(xT, _dp), _ptr(dxT, _dp), n, n,
+                               float(h), int(nsteps), nthreads), "rk4_cstep")
+    return xT, dxT
+
+
+def adjoint(sys, params, x0, lamT, h, nsteps, pp_slot=None, pparams=None, nthreads=0):
+    """Exact gradient of the FP64 map.  Returns (lam0, mu_pp, mu_global)."""
+    x0 = _f64(x0)
+    dim, n = x0.shape
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64)
+    lam = _f64(lamT).reshape(dim, n).copy()
+    mu_pp = np.zeros((npp, n)) if npp else None
+    mu_g = np.zeros(len(p))
+    _check(lib().ffo_adjoint(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                             _ptr(pp, _dp), _ptr(x0, _dp), _ptr(lam, _dp), _ptr(mu_pp, _dp),
+                             _ptr(mu_g, _dp), n, n, float(h), int(nsteps), nthreads), "adjoint")
+    return lam, mu_pp, mu_g
+
+
+def histogram(state, axis_x, axis_y, x_range, y_range, nx, ny, pparams=None,
+              hist=None, n_dropped=0):
+    """2D density projection; returns (hist[ny, nx] uint32, n_dropped).
+
+    Single-precision positions are converted exactly to double first.  Pass a
+    previous ``hist`` and ``n_dropped`` to accumulate."""
+    st = _f64(state)
+    dim, n = st.shape
+    pp = None if pparams is None else _f64(pparams).reshape(-1, n)
+    npp = 0 if pp is None else pp.shape[0]
+    acc = hist is not None
+    h = np.zeros((ny, nx), dtype=np.uint32) if hist is None else np.array(hist, dtype=np.uint32)
+    d = np.array([n_dropped], dtype=np.uint64)
+    _check(lib().ffo_histogram(dim, _ptr(st, _dp), npp, _ptr(pp, _dp), n, n, axis_x, axis_y,
+                               float(x_range[0]), float(x_range[1]), float(y_range[0]),
+                               float(y_range[1]), nx, ny, _ptr(h, _u32p), _ptr(d, _u64p),
+                               int(acc)), "histogram")
+    return h, int(d[0])

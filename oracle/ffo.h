@@ -1,0 +1,108 @@
+/*
+ * ffo.h — the CPU oracle for the Fireflies particle-RK4 hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, constant or helper with the HIP library; both sides are written
+ * independently from the paper (Merrison-Hort, "Fireflies", arXiv:1505.00344).
+ *
+ * What it computes (plain, slow, obviously correct; FP64 unless stated):
+ *   - classical fourth-order Runge-Kutta with a constant, signed step for every
+ *     particle independently (Section 2.1: one solver, RK4 with constant step;
+ *     Appendix A.1: read position, RK4 update, write back; Appendix A.2: the
+ *     step may be positive or negative);
+ *   - the right-hand sides of the paper's systems: Lorenz (Section 2.2,
+ *     Eqs. lorenz_x/y/z), a Wilson-Cowan E/I pair standing in for the
+ *     STN-GPe model (Section 2.1, Eqs. stn_gpe/eqnGPe, whose constants the
+ *     paper does not print), the Hodgkin-Huxley ring with first-order
+ *     synapses (Section 3, Eqs. hh_v/hh_h/hh_m/hh_n/hh_isyn/hh_s), linear
+ *     test systems x' = A x, and (oracle only, for pinning the tableau) the
+ *     scalar Riccati equation y' = y^2;
+ *   - per-particle parameter values, the paper's "parameter as a state with
+ *     zero derivative" bifurcation trick (Section 2.1 and Section 2.2);
+ *   - the 2D density projection as integer counts (Appendix A.1, additive
+ *     blending of unit-weight points = counting);
+ *   - the exact gradient of the discrete RK4 map (reverse mode), with the
+ *     full Jacobian and parameter Jacobian formed explicitly;
+ *   - the same RK4 map in complex arithmetic (complex-step derivative,
+ *     Squire & Trapp 1998), used to pin the adjoint;
+ *   - the same RK4 map in single precision, plain and with a Kahan-compensated
+ *     update, for bit-level checks of single-precision kernels on systems
+ *     without transcendental functions.
+ *
+ * Layout: structure of arrays.  state[d*ld + i] is component d of particle i;
+ * pparams[k*ld + i] is per-particle parameter k of particle i, which replaces
+ * global parameter pp_slot[k].  All pointers are host memory owned by the
+ * caller.  Every function returns 0 on success and a negative code on invalid
+ * arguments (nothing is written then).
+ */
+#ifndef FFO_H
+#define FFO_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { FFO_LINEAR = 0, FFO_LORENZ = 1, FFO_WILSON_COWAN = 2, FFO_HH_RING = 3, FFO_RICCATI = 100 };
+
+/* Number of global parameters a system expects for a given dimension, or -1. */
+int ffo_n_params(int sys, int dim);
+
+/* f(x) for m points x[m][dim] (row-major, one point per row) -> f[m][dim]. */
+int ffo_rhs(int sys, int dim, const double* params, int n_params,
+            const double* x, double* f, int64_t m);
+
+/* Jacobian J[m][dim][dim] (J[r][c] = d f_r / d x_c) and parameter Jacobian
+ * Fp[m][dim][n_params] at m points, both formed explicitly. */
+int ffo_jacobians(int sys, int dim, const double* params, int n_params,
+                  const double* x, double* J, double* Fp, int64_t m);
+
+/* nsteps classical RK4 steps of size h on every particle (FP64). */
+int ffo_rk4(int sys, int dim, const double* params, int n_params,
+            const int32_t* pp_slot, int n_pp, const double* pparams,
+            double* state, int64_t n, int64_t ld, double h, int64_t nsteps,
+            int nthreads);
+
+/* The same map in single precision: state/pparams are float; params are
+ * rounded to float once.  kahan != 0 uses the compensated update with the
+ * compensation array comp (same layout as state, carried in and out). */
+int ffo_rk4_f32(int sys, int dim, const double* params, int n_params,
+                const int32_t* pp_slot, int n_pp, const float* pparams,
+                float* state, float* comp, int kahan, int64_t n, int64_t ld,
+                float h, int64_t nsteps, int nthreads);
+
+/* Complex-step directional derivative of the FP64 map.  Inputs are perturbed
+ * by i*eps times the directions dx0 (SoA like state), dparams (n_params) and
+ * dpp (SoA like pparams); any direction pointer may be NULL (= zero).
+ * Outputs: xT (real part, SoA) and dxT (imaginary part / eps, SoA). */
+int ffo_rk4_cstep(int sys, int dim, const double* params, int n_params,
+                  const int32_t* pp_slot, int n_pp, const double* pparams,
+                  const double* x0, const double* dx0, const double* dparams,
+                  const double* dpp, double eps, double* xT, double* dxT,
+                  int64_t n, int64_t ld, double h, int64_t nsteps, int nthreads);
+
+/* Exact reverse-mode gradient of the FP64 map.  On entry lam[dim][ld] holds
+ * dL/dx_T; on exit dL/dx_0.  x0 is the initial state (not modified).
+ * mu_pp[n_pp][ld] receives dL/d(per-particle parameter k) (may be NULL when
+ * n_pp == 0); mu_global[n_params] receives the sum over particles of
+ * dL/d(parameter j) (may be NULL). */
+int ffo_adjoint(int sys, int dim, const double* params, int n_params,
+                const int32_t* pp_slot, int n_pp, const double* pparams,
+                const double* x0, double* lam, double* mu_pp, double* mu_global,
+                int64_t n, int64_t ld, double h, int64_t nsteps, int nthreads);
+
+/* 2D density projection.  axis >= 0 selects state component axis, axis < 0
+ * selects per-particle parameter (-1 - axis).  Half-open ranges
+ * [x_lo, x_hi) x [y_lo, y_hi) with nx x ny bins; hist[iy*nx + ix] += 1;
+ * particles outside or with NaN coordinates increment *n_dropped.
+ * accumulate == 0 clears hist and *n_dropped first. */
+int ffo_histogram(int dim, const double* state, int n_pp, const double* pparams,
+                  int64_t n, int64_t ld, int axis_x, int axis_y,
+                  double x_lo, double x_hi, double y_lo, double y_hi,
+                  int nx, int ny, uint32_t* hist, uint64_t* n_dropped,
+                  int accumulate);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
