@@ -1,0 +1,210 @@
+/*
+ * fireflies.h — C ABI of libfireflies.so, the MI355X (gfx950) hot path of
+ * "Fireflies: New software for interactively exploring dynamical systems
+ * using GPU computing" (R. Merrison-Hort, arXiv:1505.00344).
+ *
+ * The method (Section 2.1; Appendix A, Appendix A.1, Appendix A.2): many
+ * independent trajectories ("particles") of an autonomous N-dimensional ODE
+ * are advanced with the classical fourth-order Runge-Kutta method at a
+ * constant, signed step (forward groups h > 0, backward groups h < 0); a
+ * parameter may take a separate value per particle (the paper's trick of a
+ * parameter turned into a state variable with zero derivative, Section 2.1
+ * and Section 2.2); the current positions are projected onto two chosen axes
+ * and accumulated additively on a pixel grid (Appendix A "Render Technique",
+ * Appendix A.1 fragment shader with additive blending).  This library
+ * computes exactly that, with unit weight per particle (a 2D count
+ * histogram), plus the exact discrete adjoint of the RK4 map and a batched
+ * launch over ragged groups of different systems.
+ *
+ * Conventions for every function below.
+ *   - Device memory: every array argument documented as "device" is memory
+ *     of the current HIP device, owned by the caller (typically a torch
+ *     tensor).  The library never frees caller memory.
+ *   - Layout: structure of arrays.  Component d of particle i is
+ *     state[d*ld + i]; per-particle parameter k of particle i is
+ *     pparams[k*ld + i]; ld >= n.
+ *   - Element type follows ff_batch.prec: float for FF_FP32 and
+ *     FF_FP32_KAHAN, double for FF_FP64.
+ *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *     Calls only enqueue work; none synchronises the device.
+ *   - Errors: arguments are validated on the host before anything is
+ *     enqueued; on failure nothing was enqueued and ff_last_error() explains
+ *     why.  FF_E_DEVICE reports a HIP error (its text in ff_last_error()).
+ *     No call aborts the process.  NaN/Inf in the data are not errors: they
+ *     propagate through the arithmetic as IEEE values.
+ */
+#ifndef FIREFLIES_H
+#define FIREFLIES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FF_ABI_VERSION 1
+#define FF_MAX_PP 4 /* per-particle parameters per batch */
+
+typedef enum {
+    FF_OK = 0,
+    FF_E_INVALID = 1,     /* bad argument; nothing enqueued */
+    FF_E_UNSUPPORTED = 2, /* valid request this build does not implement */
+    FF_E_NOMEM = 3,       /* host or device allocation failed, or workspace too small */
+    FF_E_DEVICE = 4       /* HIP runtime error */
+} ff_status;
+
+typedef enum {
+    FF_FP32 = 0,       /* single precision */
+    FF_FP32_KAHAN = 1, /* single precision, Kahan-compensated state update */
+    FF_FP64 = 2        /* double precision */
+} ff_prec;
+
+/* Right-hand sides (all autonomous).  Parameter vectors, in order:
+ *   FF_RHS_LINEAR        x' = A x, dim 1..4; params = A row-major (dim*dim).
+ *   FF_RHS_LORENZ        Section 2.2, Eqs. lorenz_x/y/z; dim 3;
+ *                        params = [sigma, r, beta].
+ *   FF_RHS_WILSON_COWAN  E' = -E + S_E(c1 E - c2 I + P),
+ *                        I' = -I + S_I(c3 E - c4 I + Q),
+ *                        S(u) = 1/(1 + exp(-a (u - theta))): the
+ *                        sigmoid-coupled pair of Section 2.1 (Eqs.
+ *                        stn_gpe/eqnGPe) with unit time constants; dim 2;
+ *                        params = [c1, c2, c3, c4, aE, thetaE, aI, thetaI, P, Q].
+ *   FF_RHS_HH_RING       ring of N = dim/5 Hodgkin-Huxley neurons (Section 3,
+ *                        Eqs. hh_v, hh_h, hh_m, hh_n, hh_isyn, hh_s); neuron j
+ *                        is [V, m, h, n, s] at 5j and receives the synapse of
+ *                        neuron (j - 1) mod N; dim 5 or 15 in this build;
+ *                        params = [gNa, gK, gL, ENa, EK, EL, C, Iext, gsyn,
+ *                        Esyn, r_rise, r_decay, theta_syn, sigma_syn]. */
+typedef enum {
+    FF_RHS_LINEAR = 0,
+    FF_RHS_LORENZ = 1,
+    FF_RHS_WILSON_COWAN = 2,
+    FF_RHS_HH_RING = 3
+} ff_rhs;
+
+typedef struct ff_system_s* ff_system_t; /* opaque, library-owned */
+
+/* One slice of particles (a "Particle Group" of Appendix A without its
+ * initial-condition box, which is the caller's business). */
+typedef struct {
+    int32_t prec;                /* ff_prec */
+    void* state;                 /* device [dim][ld], in/out */
+    int64_t n;                   /* particles */
+    int64_t ld;                  /* leading dimension, >= n */
+    const void* pparams;         /* device [n_pp][ld], or NULL when n_pp == 0 */
+    int32_t n_pp;                /* 0..FF_MAX_PP per-particle parameters */
+    int32_t pp_slot[FF_MAX_PP];  /* pparams row k replaces global parameter pp_slot[k] */
+    void* comp;                  /* device [dim][ld] Kahan compensation (FF_FP32_KAHAN
+                                    only; carried across calls; start it at 0) */
+} ff_batch;
+
+/* Launch shape.  steps_per_launch: RK4 steps fused per kernel launch (the
+ * state stays in registers between them); particles_per_thread: 1, 2 or 4
+ * (the Hodgkin-Huxley rings are limited to 2; larger requests are clamped);
+ * block: threads per block, a multiple of 64 in [64, 256].  Results are
+ * bitwise independent of all three. */
+typedef struct {
+    int32_t steps_per_launch;
+    int32_t particles_per_thread;
+    int32_t block;
+} ff_tuning;
+
+int32_t ff_abi_version(void);
+
+/* Text of the last error on the calling thread; valid until the next ff_*
+ * call on this thread.  Never NULL. */
+const char* ff_last_error(void);
+
+/* Create a system: right-hand side, dimension, parameter count and default
+ * global parameter values (host, n_params doubles).  Host-only: touches no
+ * device.  *out receives the handle (release it with ff_system_destroy). */
+ff_status ff_system_create(int32_t rhs, int32_t dim, int32_t n_params, const double* params,
+                           ff_system_t* out);
+ff_status ff_system_destroy(ff_system_t sys);
+
+/* Replace the global parameter values (host array of n_params doubles): the
+ * paper's live slider (Appendix A.2).  Takes effect for calls enqueued
+ * afterwards. */
+ff_status ff_system_set_params(ff_system_t sys, const double* params, int32_t n_params);
+ff_status ff_system_get_params(ff_system_t sys, double* params, int32_t n_params);
+ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n_params);
+
+/* Advance every particle of the batch by nsteps classical RK4 steps of size
+ * dt_signed (Section 2.1; Appendix A.1-A.2).  In single precision the step is
+ * rounded to float once, and h/2 and h/6 are formed in float.  dt_signed == 0
+ * or nsteps == 0 (the paper's paused state) or n == 0 enqueue nothing.
+ * tuning may be NULL (defaults: all steps in one launch, library-chosen
+ * particles per thread and block size). */
+ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                       const ff_tuning* tuning, void* stream);
+
+/* 2D density projection (Appendix A "Render Technique", Appendix A.1:
+ * additive accumulation of unit-weight points).  axis >= 0 selects state
+ * component axis; axis = -1 - k selects per-particle parameter row k.  The
+ * bin of a particle is ix = floor((a - x_lo) * (nx / (x_hi - x_lo))) (and
+ * likewise iy), computed in double precision; it is kept iff 0 <= ix < nx and
+ * 0 <= iy < ny (NaN fails), and then hist[iy*nx + ix] += 1; otherwise
+ * *n_dropped += 1.  Counts are exact.  hist: device uint32 [ny][nx];
+ * n_dropped: device uint64 or NULL (not counted); accumulate == 0 first sets
+ * hist (and *n_dropped) to zero.  workspace: device scratch of at least
+ * ff_histogram_workspace_size() bytes, or NULL to use library-owned scratch
+ * (allocated on first use on the device; pass your own under stream
+ * capture). */
+ff_status ff_histogram_workspace_size(int64_t n, int32_t nx, int32_t ny, size_t* bytes);
+ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
+                               double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
+                               int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Discrete adjoint (exact gradient of the RK4 map above with respect to the
+ * initial state and the parameters; the Kahan update is differentiated as
+ * exact addition).  Usage: ff_integrate_checkpointed() advances the batch
+ * like ff_integrate() and stores the state (and compensation) every K steps
+ * in `workspace`; then ff_adjoint() walks the segments backwards, recomputing
+ * each segment from its checkpoint.
+ *   lambda:    device [dim][ld]; in dL/dx(T), out dL/dx(0)
+ *   mu:        device [n_pp][ld]; out dL/d(per-particle parameter k)
+ *              (NULL allowed when n_pp == 0)
+ *   mu_global: device double [n_params]; out sum over particles of
+ *              dL/d(parameter j) for every parameter (FP64 reduction), or NULL
+ * The batch passed to ff_adjoint must describe the same particles (its state
+ * pointer is not read).  workspace_bytes must be >= the size returned by
+ * ff_adjoint_workspace_size for the same arguments. */
+ff_status ff_adjoint_workspace_size(ff_system_t sys, const ff_batch* b, int64_t nsteps, int32_t K,
+                                    size_t* bytes);
+ff_status ff_integrate_checkpointed(ff_system_t sys, const ff_batch* b, double dt_signed,
+                                    int64_t nsteps, int32_t K, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                     int32_t K, void* workspace, size_t workspace_bytes, void* lambda, void* mu,
+                     double* mu_global, void* stream);
+
+/* Ragged batch: several particle groups (each with its own system, slice,
+ * precision and signed step) advanced nsteps in one persistent launch per
+ * steps_per_launch.  Every group must use FF_FP32 or FF_FP32_KAHAN or every
+ * group FF_FP64.  Results are bitwise equal to ff_integrate on each group.
+ * workspace: device scratch of at least ff_groups_workspace_size() bytes, or
+ * NULL for library-owned scratch. */
+typedef struct {
+    ff_system_t sys;
+    ff_batch b;
+    double dt_signed;
+} ff_group;
+
+ff_status ff_groups_workspace_size(int32_t n_groups, size_t* bytes);
+ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t nsteps,
+                              const ff_tuning* tuning, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/* Pick steps_per_launch, particles_per_thread and block for a group list by
+ * timing candidate launches (on copies of the groups' state, which is left
+ * unchanged).  steps_per_launch is searched in [10, min(500, nsteps)].
+ * Synchronises the stream.  *out receives the choice. */
+ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, ff_tuning* out,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIREFLIES_H */

@@ -1,0 +1,210 @@
+"""Python binding of libfireflies.so with the C ABI's names.
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the current stream; every step of the computation runs in the HIP
+kernels behind the C ABI.  State tensors are structure-of-arrays with shape
+``(dim, ld)`` (``ld`` >= the particle count ``n``), per-particle parameters
+``(n_pp, ld)``; float32 or float64 on a CUDA (HIP) device.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _ffi
+from ._ffi import (FF_FP32, FF_FP32_KAHAN, FF_FP64, FF_RHS_HH_RING, FF_RHS_LINEAR,
+                   FF_RHS_LORENZ, FF_RHS_WILSON_COWAN, Batch, Group, Tuning, call)
+
+RHS = {"linear": FF_RHS_LINEAR, "lorenz": FF_RHS_LORENZ, "wilson_cowan": FF_RHS_WILSON_COWAN,
+       "hh_ring": FF_RHS_HH_RING}
+PREC = {"fp32": FF_FP32, "fp32_kahan": FF_FP32_KAHAN, "fp64": FF_FP64}
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream if hasattr(s, "cuda_stream") else int(s)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class System:
+    """An ODE system handle (ff_system_create)."""
+
+    def __init__(self, rhs, dim: int, params: Sequence[float]):
+        self.rhs = RHS[rhs] if isinstance(rhs, str) else int(rhs)
+        self.dim = int(dim)
+        p = (ctypes.c_double * len(params))(*map(float, params))
+        h = ctypes.c_void_p()
+        call("ff_system_create", self.rhs, self.dim, len(params), p, ctypes.byref(h))
+        self.handle = h
+        self.n_params = len(params)
+
+    def set_params(self, params: Sequence[float]) -> None:
+        p = (ctypes.c_double * len(params))(*map(float, params))
+        call("ff_system_set_params", self.handle, p, len(params))
+
+    def get_params(self):
+        p = (ctypes.c_double * self.n_params)()
+        call("ff_system_get_params", self.handle, p, self.n_params)
+        return list(p)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        L = getattr(_ffi, "_lib", None) if _ffi is not None else None
+        if h is not None and L is not None:
+            L.ff_system_destroy(h)
+            self.handle = None
+
+
+def make_batch(state: torch.Tensor, n: Optional[int] = None, pparams: Optional[torch.Tensor] = None,
+               pp_slot: Sequence[int] = (), comp: Optional[torch.Tensor] = None,
+               prec: Optional[str] = None, offset: int = 0) -> Batch:
+    """Describe a particle slice for the C ABI (no copies): particles
+    ``offset .. offset + n - 1`` of the (dim, ld) arrays."""
+    if state.dim() != 2:
+        raise ValueError("state must have shape (dim, ld)")
+    if not state.is_contiguous():
+        raise ValueError("state must be contiguous")
+    ld = state.shape[1]
+    offset = int(offset)
+    n = ld - offset if n is None else int(n)
+    if offset < 0 or n < 0 or offset + n > ld:
+        raise ValueError("slice outside the arrays")
+    if prec is None:
+        if state.dtype == torch.float64:
+            prec = "fp64"
+        elif state.dtype == torch.float32:
+            prec = "fp32_kahan" if comp is not None else "fp32"
+        else:
+            raise ValueError("state must be float32 or float64")
+    pc = PREC[prec]
+    want = torch.float64 if pc == FF_FP64 else torch.float32
+    for name, t in (("state", state), ("pparams", pparams), ("comp", comp)):
+        if t is not None and (t.dtype != want or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {want} tensor")
+    b = Batch()
+    b.prec = pc
+    esz = state.element_size()
+    b.state = state.data_ptr() + offset * esz
+    b.n = n
+    b.ld = ld
+    slots = list(pp_slot)
+    if pparams is not None:
+        if pparams.dim() != 2 or pparams.shape[1] != ld or pparams.shape[0] != len(slots):
+            raise ValueError("pparams must have shape (len(pp_slot), ld)")
+        b.pparams = pparams.data_ptr() + offset * esz
+    elif slots:
+        raise ValueError("pp_slot given without pparams")
+    b.n_pp = len(slots)
+    for k, s in enumerate(slots):
+        b.pp_slot[k] = int(s)
+    if comp is not None:
+        if comp.shape != state.shape:
+            raise ValueError("comp must have the shape of state")
+        b.comp = comp.data_ptr() + offset * esz
+    return b
+
+
+def make_tuning(tuning) -> Optional[Tuning]:
+    if tuning is None:
+        return None
+    if isinstance(tuning, Tuning):
+        return tuning
+    s, ppt, blk = tuning
+    return Tuning(int(s), int(ppt), int(blk))
+
+
+def integrate(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, n=None, pparams=None,
+              pp_slot=(), comp=None, prec=None, tuning=None, stream=None, offset=0) -> None:
+    """ff_integrate: advance ``state`` in place by ``nsteps`` RK4 steps."""
+    b = make_batch(state, n, pparams, pp_slot, comp, prec, offset)
+    t = make_tuning(tuning)
+    call("ff_integrate", sys.handle, ctypes.byref(b), float(dt), int(nsteps),
+         ctypes.byref(t) if t is not None else None, _stream(stream))
+
+
+def histogram_workspace_size(n: int, nx: int, ny: int) -> int:
+    out = ctypes.c_size_t()
+    call("ff_histogram_workspace_size", int(n), int(nx), int(ny), ctypes.byref(out))
+    return out.value
+
+
+def project_histogram(sys: System, state: torch.Tensor, axis_x: int, axis_y: int, x_range, y_range,
+                      nx: int, ny: int, *, hist: Optional[torch.Tensor] = None,
+                      n_dropped: Optional[torch.Tensor] = None, accumulate: bool = False, n=None,
+                      pparams=None, pp_slot=(), prec=None, workspace: Optional[torch.Tensor] = None,
+                      stream=None, offset=0):
+    """ff_project_histogram: returns (hist uint32 (ny, nx) as int32 view, n_dropped)."""
+    b = make_batch(state, n, pparams, pp_slot, None, prec if prec != "fp32_kahan" else "fp32", offset)
+    dev = state.device
+    if hist is None:
+        hist = torch.empty((ny, nx), dtype=torch.int32, device=dev)
+    if n_dropped is None:
+        n_dropped = torch.empty(1, dtype=torch.int64, device=dev)
+    ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel() * workspace.element_size())
+    call("ff_project_histogram", sys.handle, ctypes.byref(b), int(axis_x), int(axis_y),
+         float(x_range[0]), float(x_range[1]), float(y_range[0]), float(y_range[1]), int(nx), int(ny),
+         hist.data_ptr(), n_dropped.data_ptr(), int(bool(accumulate)), ws_ptr, ws_bytes, _stream(stream))
+    return hist, n_dropped
+
+
+def adjoint_workspace_size(sys: System, state: torch.Tensor, nsteps: int, K: int, *, n=None,
+                           pparams=None, pp_slot=(), comp=None, prec=None) -> int:
+    b = make_batch(state, n, pparams, pp_slot, comp, prec)
+    out = ctypes.c_size_t()
+    call("ff_adjoint_workspace_size", sys.handle, ctypes.byref(b), int(nsteps), int(K), ctypes.byref(out))
+    return out.value
+
+
+def integrate_checkpointed(sys: System, state: torch.Tensor, dt: float, nsteps: int, K: int,
+                           workspace: torch.Tensor, *, n=None, pparams=None, pp_slot=(), comp=None,
+                           prec=None, stream=None) -> None:
+    b = make_batch(state, n, pparams, pp_slot, comp, prec)
+    call("ff_integrate_checkpointed", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(K),
+         workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream))
+
+
+def adjoint(sys: System, state: torch.Tensor, dt: float, nsteps: int, K: int, workspace: torch.Tensor,
+            lam: torch.Tensor, *, mu: Optional[torch.Tensor] = None,
+            mu_global: Optional[torch.Tensor] = None, n=None, pparams=None, pp_slot=(), comp=None,
+            prec=None, stream=None) -> None:
+    """ff_adjoint: ``lam`` holds dL/dx(T) on entry and dL/dx(0) on exit."""
+    b = make_batch(state, n, pparams, pp_slot, comp, prec)
+    call("ff_adjoint", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(K), workspace.data_ptr(),
+         workspace.numel() * workspace.element_size(), lam.data_ptr(), _ptr(mu), _ptr(mu_global),
+         _stream(stream))
+
+
+def make_groups(specs) -> "ctypes.Array":
+    """specs: iterable of (System, Batch, dt)."""
+    specs = list(specs)
+    arr = (Group * len(specs))()
+    for g, (sys, b, dt) in zip(arr, specs):
+        g.sys = sys.handle
+        g.b = b
+        g.dt_signed = float(dt)
+    return arr
+
+
+def groups_workspace_size(n_groups: int) -> int:
+    out = ctypes.c_size_t()
+    call("ff_groups_workspace_size", int(n_groups), ctypes.byref(out))
+    return out.value
+
+
+def integrate_groups(groups, nsteps: int, *, tuning=None, workspace: Optional[torch.Tensor] = None,
+                     stream=None) -> None:
+    t = make_tuning(tuning)
+    ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel() * workspace.element_size())
+    call("ff_integrate_groups", groups, len(groups), int(nsteps),
+         ctypes.byref(t) if t is not None else None, ws_ptr, ws_bytes, _stream(stream))
+
+
+def autotune(groups, nsteps: int, stream=None) -> Tuning:
+    out = Tuning()
+    call("ff_autotune", groups, len(groups), int(nsteps), ctypes.byref(out), _stream(stream))
+    return out

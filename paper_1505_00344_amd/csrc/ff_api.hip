@@ -1,0 +1,221 @@
+// ff_api.hip — C ABI: system handles, validation, errors, and ff_integrate.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ff_internal.h"
+
+namespace ff {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+ff_status fail(ff_status code, const std::string& msg) {
+    g_error = msg;
+    return code;
+}
+
+ff_status device_fail(hipError_t e, const char* where) {
+    return fail(FF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t prec_size(int prec) { return prec == FF_FP64 ? sizeof(double) : sizeof(float); }
+
+static int expected_params(int rhs, int dim) {
+    switch (rhs) {
+        case FF_RHS_LINEAR: return (dim >= 1 && dim <= 4) ? dim * dim : -1;
+        case FF_RHS_LORENZ: return dim == 3 ? 3 : -1;
+        case FF_RHS_WILSON_COWAN: return dim == 2 ? 10 : -1;
+        case FF_RHS_HH_RING: return (dim == 5 || dim == 15) ? 14 : -1;
+    }
+    return -1;
+}
+
+ff_status check_system(const ff_system_s* sys) {
+    if (!sys) return fail(FF_E_INVALID, "system handle is NULL");
+    return FF_OK;
+}
+
+ff_status check_batch(const ff_system_s* sys, const ff_batch* b, bool need_state) {
+    if (!b) return fail(FF_E_INVALID, "batch is NULL");
+    if (b->prec != FF_FP32 && b->prec != FF_FP32_KAHAN && b->prec != FF_FP64)
+        return fail(FF_E_INVALID, "batch.prec must be FF_FP32, FF_FP32_KAHAN or FF_FP64");
+    if (b->n < 0) return fail(FF_E_INVALID, "batch.n < 0");
+    if (b->ld < b->n) return fail(FF_E_INVALID, "batch.ld < batch.n");
+    if (b->ld > 0 && (int64_t)sys->dim > INT64_MAX / b->ld)
+        return fail(FF_E_INVALID, "dim * ld overflows");
+    if (b->n_pp < 0 || b->n_pp > FF_MAX_PP)
+        return fail(FF_E_INVALID, "batch.n_pp must be in [0, FF_MAX_PP]");
+    for (int k = 0; k < b->n_pp; ++k)
+        if (b->pp_slot[k] < 0 || b->pp_slot[k] >= sys->n_params)
+            return fail(FF_E_INVALID, "batch.pp_slot[" + std::to_string(k) + "] = " +
+                                          std::to_string(b->pp_slot[k]) + " is not a parameter index");
+    for (int k = 0; k < b->n_pp; ++k)
+        for (int l = 0; l < k; ++l)
+            if (b->pp_slot[k] == b->pp_slot[l])
+                return fail(FF_E_INVALID, "batch.pp_slot repeats parameter " + std::to_string(b->pp_slot[k]));
+    if (b->n > 0) {
+        if (need_state && !b->state) return fail(FF_E_INVALID, "batch.state is NULL");
+        if (b->n_pp > 0 && !b->pparams) return fail(FF_E_INVALID, "batch.pparams is NULL but n_pp > 0");
+        if (need_state && b->prec == FF_FP32_KAHAN && !b->comp)
+            return fail(FF_E_INVALID, "FF_FP32_KAHAN needs batch.comp");
+    }
+    return FF_OK;
+}
+
+ff_status check_tuning(const ff_system_s* sys, const ff_tuning* t) {
+    if (!t) return FF_OK;
+    if (t->steps_per_launch < 1) return fail(FF_E_INVALID, "tuning.steps_per_launch < 1");
+    if (t->particles_per_thread != 1 && t->particles_per_thread != 2 && t->particles_per_thread != 4)
+        return fail(FF_E_INVALID, "tuning.particles_per_thread must be 1, 2 or 4");
+    if (t->block < 64 || t->block > 256 || t->block % 64 != 0)
+        return fail(FF_E_INVALID, "tuning.block must be 64, 128, 192 or 256");
+    (void)sys;
+    return FF_OK;
+}
+
+ff_tuning default_tuning(const ff_system_s* sys, int prec, int64_t nsteps) {
+    ff_tuning t;
+    t.steps_per_launch = (int32_t)(nsteps < 4096 ? (nsteps > 0 ? nsteps : 1) : 4096);
+    t.block = 256;
+    t.particles_per_thread = 1;
+    if (sys->rhs == FF_RHS_HH_RING) t.block = 128;
+    (void)prec;
+    return t;
+}
+
+RK4Launch make_launch(const ff_system_s* sys, const ff_batch* b, double dt, const ff_tuning* t,
+                      hipStream_t stream) {
+    RK4Launch L;
+    std::memset(&L, 0, sizeof L);
+    L.prec = b->prec;
+    L.state = b->state;
+    L.comp = b->comp;
+    L.pp = b->pparams;
+    L.n = b->n;
+    L.ld = b->ld;
+    L.n_pp = b->n_pp;
+    for (int k = 0; k < kMaxPP; ++k) L.slot[k] = k < b->n_pp ? b->pp_slot[k] : -1;
+    for (int q = 0; q < kMaxParams; ++q) L.p.v[q] = q < sys->n_params ? sys->params[q] : 0.0;
+    if (b->prec == FF_FP64) {
+        L.h = dt;
+        L.h2 = dt * 0.5;
+        L.h6 = dt / 6.0;
+    } else {
+        const float h = (float)dt;
+        const float h2 = h * 0.5f;
+        const float h6 = h / 6.0f;
+        L.h = h;
+        L.h2 = h2;
+        L.h6 = h6;
+    }
+    L.ppt = t->particles_per_thread;
+    L.block = t->block;
+    L.stream = stream;
+    return L;
+}
+
+hipError_t launch_rk4(const ff_system_s* sys, const RK4Launch& L) {
+    switch (sys->rhs) {
+        case FF_RHS_LINEAR: return launch_rk4_linear(sys->dim, L);
+        case FF_RHS_LORENZ: return launch_rk4_lorenz(L);
+        case FF_RHS_WILSON_COWAN: return launch_rk4_wc(L);
+        case FF_RHS_HH_RING: return launch_rk4_hh(sys->dim / 5, L);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+int32_t ff_abi_version(void) { return FF_ABI_VERSION; }
+
+const char* ff_last_error(void) { return g_error.c_str(); }
+
+ff_status ff_system_create(int32_t rhs, int32_t dim, int32_t n_params, const double* params,
+                           ff_system_t* out) {
+    g_error.clear();
+    if (!out) return fail(FF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int want = expected_params(rhs, dim);
+    if (want < 0) {
+        if (rhs < 0 || rhs > FF_RHS_HH_RING) return fail(FF_E_INVALID, "unknown right-hand side");
+        if (rhs == FF_RHS_HH_RING && dim > 0 && dim % 5 == 0)
+            return fail(FF_E_UNSUPPORTED, "Hodgkin-Huxley ring: this build has 1 or 3 neurons (dim 5 or 15)");
+        return fail(FF_E_INVALID, "dimension " + std::to_string(dim) + " does not fit the right-hand side");
+    }
+    if (n_params != want)
+        return fail(FF_E_INVALID, "right-hand side expects " + std::to_string(want) + " parameters, got " +
+                                      std::to_string(n_params));
+    if (!params) return fail(FF_E_INVALID, "params is NULL");
+    ff_system_s* s = new (std::nothrow) ff_system_s;
+    if (!s) return fail(FF_E_NOMEM, "out of host memory");
+    s->rhs = rhs;
+    s->dim = dim;
+    s->n_params = n_params;
+    for (int q = 0; q < kMaxParams; ++q) s->params[q] = q < n_params ? params[q] : 0.0;
+    *out = s;
+    return FF_OK;
+}
+
+ff_status ff_system_destroy(ff_system_t sys) {
+    g_error.clear();
+    delete sys;
+    return FF_OK;
+}
+
+ff_status ff_system_set_params(ff_system_t sys, const double* params, int32_t n_params) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (!params) return fail(FF_E_INVALID, "params is NULL");
+    if (n_params != sys->n_params) return fail(FF_E_INVALID, "wrong parameter count");
+    for (int q = 0; q < n_params; ++q) sys->params[q] = params[q];
+    return FF_OK;
+}
+
+ff_status ff_system_get_params(ff_system_t sys, double* params, int32_t n_params) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (!params) return fail(FF_E_INVALID, "params is NULL");
+    if (n_params != sys->n_params) return fail(FF_E_INVALID, "wrong parameter count");
+    for (int q = 0; q < n_params; ++q) params[q] = sys->params[q];
+    return FF_OK;
+}
+
+ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n_params) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (rhs) *rhs = sys->rhs;
+    if (dim) *dim = sys->dim;
+    if (n_params) *n_params = sys->n_params;
+    return FF_OK;
+}
+
+ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                       const ff_tuning* tuning, void* stream) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (ff_status s = check_batch(sys, b, true)) return s;
+    if (ff_status s = check_tuning(sys, tuning)) return s;
+    if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
+    if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
+    if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
+    RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
+    for (int64_t done = 0; done < nsteps;) {
+        L.steps = nsteps - done < t.steps_per_launch ? nsteps - done : t.steps_per_launch;
+        const hipError_t e = launch_rk4(sys, L);
+        if (e != hipSuccess) return device_fail(e, "ff_integrate launch");
+        done += L.steps;
+    }
+    return FF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// ff_rhs.h — device right-hand sides of the particle systems, and their
+// vector-Jacobian products, for the gfx950 kernels.
+//
+// Each system is a struct template over the working precision R with
+//   D   number of state components,  NP  number of parameters,
+//   f(p, x, out)                 the right-hand side (autonomous: no t),
+//   vjp(p, x, a, gx, gp)         gx += J(x)^T a, gp += (df/dp)^T a.
+// Parameters live in a per-particle register array p[NP] (global values with
+// per-particle overrides already applied).
+//
+// Evaluation order is fixed (explicit fma(), compiled with
+// -ffp-contract=off) so that FP64 runs reproduce a CPU evaluation of the same
+// formulas operation for operation:
+//   Lorenz:  fx = s*(y - x); fy = fma(x, r - z, -y); fz = fma(x, y, -(b*z))
+//   WC:      u = fma(c1, E, fma(-c2, I, P)); S = 1/(1 + exp(-(a*(u - th))))
+//   HH:      rates with multiplications by the doubles nearest -1/10, -1/18,
+//            -1/20, -1/80; membrane sum ((((IL + INa) + IK) + Isyn) + Iext)*(1/C)
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ff {
+
+// ---------------------------------------------------------------- math
+template <typename R> struct M;
+template <> struct M<double> {
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
+};
+template <> struct M<float> {
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+    static __device__ __forceinline__ float rcp_(float x) { return 1.0f / x; }
+    static __device__ __forceinline__ float div_(float a, float b) { return a / b; }
+};
+
+// ---------------------------------------------------------------- linear
+// x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.
+template <typename R, int Dm> struct Linear {
+    static constexpr int D = Dm, NP = Dm * Dm;
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            R acc = p[r * D] * x[0];
+#pragma unroll
+            for (int c = 1; c < D; ++c) acc = M<R>::fma_(p[r * D + c], x[c], acc);
+            o[r] = acc;
+        }
+    }
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
+                                               R (&gx)[D], R (&gp)[NP]) {
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                gx[c] += p[r * D + c] * a[r];
+                gp[r * D + c] += x[c] * a[r];
+            }
+    }
+};
+
+// ---------------------------------------------------------------- Lorenz
+// Section 2.2: x' = s (y - x), y' = x (r - z) - y, z' = x y - b z; p = [s, r, b].
+template <typename R> struct Lorenz {
+    static constexpr int D = 3, NP = 3;
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+        o[0] = p[0] * (x[1] - x[0]);
+        o[1] = M<R>::fma_(x[0], p[1] - x[2], -x[1]);
+        o[2] = M<R>::fma_(x[0], x[1], -(p[2] * x[2]));
+    }
+    // J = [[-s, s, 0], [r - z, -1, -x], [y, x, -b]];  df/dp = diag-like
+    // (y - x, x, -z) on (s, r, b).
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
+                                               R (&gx)[D], R (&gp)[NP]) {
+        gx[0] += -p[0] * a[0] + (p[1] - x[2]) * a[1] + x[1] * a[2];
+        gx[1] += p[0] * a[0] - a[1] + x[0] * a[2];
+        gx[2] += -x[0] * a[1] - p[2] * a[2];
+        gp[0] += (x[1] - x[0]) * a[0];
+        gp[1] += x[0] * a[1];
+        gp[2] += -x[2] * a[2];
+    }
+};
+
+// ---------------------------------------------------------------- Wilson-Cowan
+// E' = -E + S_E(c1 E - c2 I + P), I' = -I + S_I(c3 E - c4 I + Q),
+// S(u) = 1/(1 + exp(-a (u - th)));  p = [c1, c2, c3, c4, aE, thE, aI, thI, P, Q].
+template <typename R> struct WilsonCowan {
+    static constexpr int D = 2, NP = 10;
+    static __device__ __forceinline__ R sig(R a, R u, R th) {
+        return M<R>::rcp_(R(1) + M<R>::exp_(-(a * (u - th))));
+    }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+        const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
+        const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
+        o[0] = sig(p[4], uE, p[5]) - x[0];
+        o[1] = sig(p[6], uI, p[7]) - x[1];
+    }
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
+                                               R (&gx)[D], R (&gp)[NP]) {
+        const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
+        const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
+        const R sE = sig(p[4], uE, p[5]), sI = sig(p[6], uI, p[7]);
+        const R qE = sE * (R(1) - sE), qI = sI * (R(1) - sI);
+        const R dE = p[4] * qE * a[0];   // dS_E/du_E * a_E
+        const R dI = p[6] * qI * a[1];
+        gx[0] += p[0] * dE - a[0] + p[2] * dI;
+        gx[1] += -p[1] * dE - p[3] * dI - a[1];
+        gp[0] += dE * x[0];
+        gp[1] += -dE * x[1];
+        gp[2] += dI * x[0];
+        gp[3] += -dI * x[1];
+        gp[4] += (uE - p[5]) * qE * a[0];
+        gp[5] += -dE;
+        gp[6] += (uI - p[7]) * qI * a[1];
+        gp[7] += -dI;
+        gp[8] += dE;
+        gp[9] += dI;
+    }
+};
+
+// ---------------------------------------------------------------- HH ring
+// N Hodgkin-Huxley neurons (Section 3) with first-order synapses; neuron j is
+// [V, m, h, n, s] at 5j and receives the synapse of neuron (j + N - 1) % N.
+// p = [gNa, gK, gL, ENa, EK, EL, C, Iext, gsyn, Esyn, r_rise, r_decay,
+//      th_syn, sg_syn].  Rates (modern convention, rest near -65 mV):
+//   am = psi(-(V+40)/10), bm = 4 e^{-(V+65)/18}, ah = 0.07 e^{-(V+65)/20},
+//   bh = 1/(1 + e^{-(V+35)/10}), an = 0.1 psi(-(V+55)/10),
+//   bn = 0.125 e^{-(V+65)/80},  T = 1/(1 + e^{-sg (V - th)}),
+//   psi(u) = u / (e^u - 1) with psi(0) = 1 taken by a select.
+template <typename R> struct HHRate {
+    R am, bm, ah, bh, an, bn, tv;
+};
+
+template <typename R>
+__device__ __forceinline__ R hh_psi(R u) {
+    const R q = M<R>::div_(u, M<R>::expm1_(u));
+    return (u == R(0)) ? R(1) : q;
+}
+
+template <typename R>
+__device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg) {
+    const R c10 = R(-1.0 / 10.0), c18 = R(-1.0 / 18.0), c20 = R(-1.0 / 20.0), c80 = R(-1.0 / 80.0);
+    const R v65 = V + R(65.0);
+    HHRate<R> q;
+    q.am = hh_psi<R>((V + R(40.0)) * c10);
+    q.bm = R(4.0) * M<R>::exp_(v65 * c18);
+    q.ah = R(0.07) * M<R>::exp_(v65 * c20);
+    q.bh = M<R>::rcp_(R(1) + M<R>::exp_((V + R(35.0)) * c10));
+    q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
+    q.bn = R(0.125) * M<R>::exp_(v65 * c80);
+    q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
+    return q;
+}
+
+template <typename R, int N> struct HHRing {
+    static constexpr int D = 5 * N, NP = 14;
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+        const R invC = M<R>::rcp_(p[6]);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const R V = x[5 * j], m = x[5 * j + 1], h = x[5 * j + 2], n = x[5 * j + 3], s = x[5 * j + 4];
+            const R spre = x[5 * ((j + N - 1) % N) + 4];
+            const HHRate<R> q = hh_rates<R>(V, p[12], p[13]);
+            const R IL = p[2] * (p[5] - V);
+            const R INa = ((p[0] * ((m * m) * m)) * h) * (p[3] - V);
+            const R n2 = n * n;
+            const R IK = (p[1] * (n2 * n2)) * (p[4] - V);
+            const R Is = (p[8] * spre) * (p[9] - V);
+            o[5 * j] = ((((IL + INa) + IK) + Is) + p[7]) * invC;
+            o[5 * j + 1] = M<R>::fma_(q.am, R(1) - m, -(q.bm * m));
+            o[5 * j + 2] = M<R>::fma_(q.ah, R(1) - h, -(q.bh * h));
+            o[5 * j + 3] = M<R>::fma_(q.an, R(1) - n, -(q.bn * n));
+            o[5 * j + 4] = M<R>::fma_(p[10] * q.tv, R(1) - s, -(p[11] * s));
+        }
+    }
+    // psi'(u) = (expm1(u) - u e^u) / expm1(u)^2, psi'(0) = -1/2.
+    static __device__ __forceinline__ R dpsi(R u) {
+        const R em1 = M<R>::expm1_(u);
+        const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
+        return (u == R(0)) ? R(-0.5) : d;
+    }
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
+                                               R (&gx)[D], R (&gp)[NP]) {
+        const R invC = M<R>::rcp_(p[6]);
+        const R th = p[12], sg = p[13];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int o = 5 * j, q5 = 5 * ((j + N - 1) % N);
+            const R V = x[o], m = x[o + 1], h = x[o + 2], n = x[o + 3], s = x[o + 4];
+            const R spre = x[q5 + 4];
+            const HHRate<R> q = hh_rates<R>(V, th, sg);
+            const R um = (V + R(40.0)) * R(-1.0 / 10.0), un = (V + R(55.0)) * R(-1.0 / 10.0);
+            const R dam = dpsi(um) * R(-0.1);
+            const R dbm = q.bm * R(-1.0 / 18.0);
+            const R dah = q.ah * R(-1.0 / 20.0);
+            const R dbh = R(0.1) * q.bh * (R(1) - q.bh);
+            const R dan = R(0.1) * dpsi(un) * R(-0.1);
+            const R dbn = q.bn * R(-1.0 / 80.0);
+            const R dT = sg * q.tv * (R(1) - q.tv);
+            const R m2 = m * m, m3 = m2 * m, n2 = n * n, n3 = n2 * n, n4 = n2 * n2;
+            const R eNa = p[3] - V, eK = p[4] - V, eL = p[5] - V, eS = p[9] - V;
+            const R aV = a[o] * invC;      // membrane adjoint scaled by 1/C
+            const R am_ = a[o + 1], ah_ = a[o + 2], an_ = a[o + 3], as_ = a[o + 4];
+            // d/dV
+            gx[o] += aV * (-p[2] - p[0] * m3 * h - p[1] * n4 - p[8] * spre)
+                   + am_ * (dam * (R(1) - m) - dbm * m)
+                   + ah_ * (dah * (R(1) - h) - dbh * h)
+                   + an_ * (dan * (R(1) - n) - dbn * n)
+                   + as_ * (p[10] * dT * (R(1) - s));
+            gx[o + 1] += aV * (R(3) * p[0] * m2 * h * eNa) - am_ * (q.am + q.bm);
+            gx[o + 2] += aV * (p[0] * m3 * eNa) - ah_ * (q.ah + q.bh);
+            gx[o + 3] += aV * (R(4) * p[1] * n3 * eK) - an_ * (q.an + q.bn);
+            gx[o + 4] += -as_ * (p[10] * q.tv + p[11]);
+            gx[q5 + 4] += aV * (p[8] * eS);
+            // parameters
+            const R dV = (p[2] * eL + p[0] * m3 * h * eNa + p[1] * n4 * eK + p[8] * spre * eS + p[7]) * invC;
+            gp[0] += aV * m3 * h * eNa;
+            gp[1] += aV * n4 * eK;
+            gp[2] += aV * eL;
+            gp[3] += aV * p[0] * m3 * h;
+            gp[4] += aV * p[1] * n4;
+            gp[5] += aV * p[2];
+            gp[6] += -aV * dV;
+            gp[7] += aV;
+            gp[8] += aV * spre * eS;
+            gp[9] += aV * p[8] * spre;
+            const R tq = q.tv * (R(1) - q.tv);
+            gp[10] += as_ * q.tv * (R(1) - s);
+            gp[11] += -as_ * s;
+            gp[12] += as_ * p[10] * (R(1) - s) * (-sg * tq);
+            gp[13] += as_ * p[10] * (R(1) - s) * ((V - th) * tq);
+        }
+    }
+};
+
+}  // namespace ff

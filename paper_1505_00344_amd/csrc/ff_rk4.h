@@ -1,0 +1,207 @@
+// ff_rk4.h — the fused classical-RK4 particle kernel for gfx950.
+//
+// One thread owns PPT particles.  Particle i of block b, slot j, is
+//   i = b * (blockDim * PPT) + j * blockDim + threadIdx.x,
+// so every load and store of a component row state[d*ld + i] is a coalesced,
+// contiguous 64-lane access.  The state (and the Kahan compensation) is read
+// once, advanced `steps` RK4 steps entirely in VGPRs, and written once: the
+// HBM traffic of a launch is 2*D*sizeof(R) bytes per particle (+ parameters,
+// + compensation) whatever the number of fused steps, so for steps >= ~8 the
+// kernel is bound by the vector ALU, not by HBM.
+//
+// Step (Section 2.1 / Appendix A.1: classical fourth-order Runge-Kutta with a
+// constant, signed step h), written to keep few registers live while
+// preserving the order of operations
+//   s = k2 + k3; s = fma(2, s, k1); s = s + k4; x = fma(h6, s, x):
+//   k1 = f(x); y = fma(h2,k1,x); k = f(y) [k2]; y = fma(h2,k,x); acc = k;
+//   k = f(y) [k3]; y = fma(h,k,x); acc = acc + k; acc = fma(2,acc,k1);
+//   k = f(y) [k4]; acc = acc + k; update.
+// Kahan-compensated update (single precision): inc = h6*acc; y = inc - c;
+// t = x + y; c = (t - x) - y; x = t.
+#pragma once
+#include "ff_internal.h"
+#include "ff_rhs.h"
+
+namespace ff {
+
+template <class S, typename R, bool KAHAN>
+__device__ __forceinline__ void rk4_step(const R (&p)[S::NP], R (&x)[S::D], R (&c)[S::D], R h, R h2,
+                                         R h6) {
+    constexpr int D = S::D;
+    R k1[D], k[D], y[D], acc[D];
+    S::f(p, x, k1);
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = M<R>::fma_(h2, k1[d], x[d]);
+    S::f(p, y, k);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        y[d] = M<R>::fma_(h2, k[d], x[d]);
+        acc[d] = k[d];
+    }
+    S::f(p, y, k);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        y[d] = M<R>::fma_(h, k[d], x[d]);
+        acc[d] = acc[d] + k[d];
+        acc[d] = M<R>::fma_(R(2), acc[d], k1[d]);
+    }
+    S::f(p, y, k);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        acc[d] = acc[d] + k[d];
+        if constexpr (KAHAN) {
+            const R inc = h6 * acc[d];
+            const R yk = inc - c[d];
+            const R t = x[d] + yk;
+            c[d] = (t - x[d]) - yk;
+            x[d] = t;
+        } else {
+            x[d] = M<R>::fma_(h6, acc[d], x[d]);
+        }
+    }
+}
+
+struct RK4Args {
+    void* state;
+    void* comp;
+    const void* pp;
+    int64_t n, ld;
+    int n_pp;
+    int slot[kMaxPP];
+    ParamBlock p;
+    double h, h2, h6;
+    int64_t steps;
+    void* ckpt;
+    void* ckpt_c;
+    int64_t ckpt_ld;
+};
+
+// Apply per-particle overrides with compile-time indices only, so the
+// parameter array stays in registers (no scratch).
+template <class S, typename R>
+__device__ __forceinline__ void load_params(const RK4Args& a, int64_t i, R (&p)[S::NP]) {
+    const R* pp = static_cast<const R*>(a.pp);
+    R v[kMaxPP];
+#pragma unroll
+    for (int k = 0; k < kMaxPP; ++k) v[k] = (k < a.n_pp) ? pp[k * a.ld + i] : R(0);
+#pragma unroll
+    for (int q = 0; q < S::NP; ++q) {
+        R val = R(a.p.v[q]);
+#pragma unroll
+        for (int k = 0; k < kMaxPP; ++k)
+            if (k < a.n_pp && a.slot[k] == q) val = v[k];
+        p[q] = val;
+    }
+}
+
+// Advance the tile of blockDim*PPT particles starting at particle `first`.
+// Shared by the one-group launch (k_rk4) and the persistent ragged-batch
+// launch, so both produce the same bits.
+template <class S, typename R, bool KAHAN, int PPT>
+__device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first) {
+    constexpr int D = S::D;
+    R* st = static_cast<R*>(a.state);
+    R* cp = static_cast<R*>(a.comp);
+    const int64_t base = first + threadIdx.x;
+    R x[PPT][D], c[PPT][D], p[PPT][S::NP];
+    int64_t idx[PPT];
+    bool act[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int64_t i = base + (int64_t)j * blockDim.x;
+        act[j] = i < a.n;
+        idx[j] = act[j] ? i : a.n - 1;  // n >= 1: inactive lanes shadow a valid particle
+        load_params<S, R>(a, idx[j], p[j]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            x[j][d] = st[d * a.ld + idx[j]];
+            c[j][d] = KAHAN ? cp[d * a.ld + idx[j]] : R(0);
+        }
+    }
+    if (a.ckpt) {  // checkpointed forward: keep the starting state of this launch
+        R* ck = static_cast<R*>(a.ckpt);
+        R* ckc = static_cast<R*>(a.ckpt_c);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            if (!act[j]) continue;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                ck[d * a.ckpt_ld + idx[j]] = x[j][d];
+                if (KAHAN) ckc[d * a.ckpt_ld + idx[j]] = c[j][d];
+            }
+        }
+    }
+    const R h = R(a.h), h2 = R(a.h2), h6 = R(a.h6);
+    for (int64_t s = 0; s < a.steps; ++s) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) rk4_step<S, R, KAHAN>(p[j], x[j], c[j], h, h2, h6);
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (!act[j]) continue;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            st[d * a.ld + idx[j]] = x[j][d];
+            if (KAHAN) cp[d * a.ld + idx[j]] = c[j][d];
+        }
+    }
+}
+
+template <class S, typename R, bool KAHAN, int PPT>
+__global__ void __launch_bounds__(256) k_rk4(RK4Args a) {
+    rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
+}
+
+inline RK4Args make_args(const RK4Launch& L) {
+    RK4Args a;
+    a.state = L.state;
+    a.comp = L.comp;
+    a.pp = L.pp;
+    a.n = L.n;
+    a.ld = L.ld;
+    a.n_pp = L.n_pp;
+    for (int k = 0; k < kMaxPP; ++k) a.slot[k] = L.slot[k];
+    a.p = L.p;
+    a.h = L.h;
+    a.h2 = L.h2;
+    a.h6 = L.h6;
+    a.steps = L.steps;
+    a.ckpt = L.ckpt;
+    a.ckpt_c = L.ckpt_c;
+    a.ckpt_ld = L.ckpt_ld;
+    return a;
+}
+
+template <class S, typename R, bool KAHAN, int PPT>
+hipError_t launch_rk4_t(const RK4Launch& L) {
+    const int64_t per_block = (int64_t)L.block * PPT;
+    const int64_t grid = (L.n + per_block - 1) / per_block;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rk4<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
+                       make_args(L));
+    return hipGetLastError();
+}
+
+// Dispatch over precision and particles per thread (PPT above MAXPPT is
+// clamped to MAXPPT).
+template <template <typename> class SysT, int MAXPPT>
+hipError_t dispatch_rk4(const RK4Launch& L) {
+    const int ppt = L.ppt > MAXPPT ? MAXPPT : L.ppt;
+    switch (L.prec) {
+        case FF_FP64:
+            if (ppt >= 4 && MAXPPT >= 4) return launch_rk4_t<SysT<double>, double, false, (MAXPPT >= 4 ? 4 : 1)>(L);
+            if (ppt >= 2 && MAXPPT >= 2) return launch_rk4_t<SysT<double>, double, false, (MAXPPT >= 2 ? 2 : 1)>(L);
+            return launch_rk4_t<SysT<double>, double, false, 1>(L);
+        case FF_FP32:
+            if (ppt >= 4 && MAXPPT >= 4) return launch_rk4_t<SysT<float>, float, false, (MAXPPT >= 4 ? 4 : 1)>(L);
+            if (ppt >= 2 && MAXPPT >= 2) return launch_rk4_t<SysT<float>, float, false, (MAXPPT >= 2 ? 2 : 1)>(L);
+            return launch_rk4_t<SysT<float>, float, false, 1>(L);
+        case FF_FP32_KAHAN:
+            if (ppt >= 4 && MAXPPT >= 4) return launch_rk4_t<SysT<float>, float, true, (MAXPPT >= 4 ? 4 : 1)>(L);
+            if (ppt >= 2 && MAXPPT >= 2) return launch_rk4_t<SysT<float>, float, true, (MAXPPT >= 2 ? 2 : 1)>(L);
+            return launch_rk4_t<SysT<float>, float, true, 1>(L);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ff

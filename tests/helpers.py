@@ -1,0 +1,40 @@
+"""Helpers shared by the GPU tests (no arithmetic of the method here)."""
+import numpy as np
+
+DEV = "cuda:0"
+
+
+def api():
+    from paper_1505_00344_amd import api as A
+    A._ffi.lib()
+    return A
+
+
+def to_dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def to_host(t):
+    return t.detach().cpu().numpy()
+
+
+def mixed_error(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(x - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1.0)
+
+
+def quantiles(e):
+    e = np.asarray(e)
+    return dict(median=float(np.median(e)), p99=float(np.quantile(e, 0.99)), max=float(e.max()))
+
+
+def f32_inputs(x):
+    """Round an FP64 input array to FP32 and back (exact), so that FP32 and
+    FP64 runs start from the same values."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def finite_cols(x):
+    return np.all(np.isfinite(x), axis=0)
