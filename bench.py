@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the Fireflies hot path on one MI355X.
+
+Workload (one "step" = one pass of the hot path over the ensemble):
+  Wilson-Cowan dynamic bifurcation diagram, 4,194,304 particles (per-particle
+  P ~ U[-2, 4], (E, I) ~ U[0, 1]^2), half integrated forward (h = +0.01) and
+  half backward (h = -0.01), 1000 classical RK4 steps in the FP32
+  Kahan-compensated precision, then the 1024 x 1024 (P, E) density grid.
+  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is particle-RK4-steps/s of the whole step
+(P * 1000 / step time).  `roofline` is for the dominant kernel (the fused
+RK4 kernel): algorithmic FLOPs per launch / its average duration from HIP
+events recorded on the stream it runs on.  `cpu_baseline` times the CPU
+oracle (FP64, all host threads) on a bounded sample of the same ensemble.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per particle-step (counted from the canonical formulas;
+# exp and a division each count as one operation, a fused multiply-add as 2):
+#   Wilson-Cowan RHS per component: 2 fma + sub + mul + exp + add + div + sub
+#   = 10 -> 20 per evaluation (16 FLOP + 2 exp + 2 div), 4 evaluations = 80;
+#   stage points 3 x 2 fma = 12; combination per component add + fma + add +
+#   fma = 6 -> 12.  Plain: 104.  Kahan update replaces the final fma (2) by
+#   mul, sub, add, sub, sub (5): +3 per component -> 110.
+FLOP_PER_STEP = {"wilson_cowan": {"fp32": 104, "fp32_kahan": 110, "fp64": 104},
+                 "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68}}
+PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
+METRIC = "particle-RK4-steps/s (FP32-comp vs FP64) + % VALU peak; adjoint steps/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--particles", type=int, default=4 * 1024 * 1024)
+    ap.add_argument("--rk4-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work for the baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}), flush=True)
+        print("bench.py: only --gpus 1 is supported (the method shards trivially over particles; "
+              "the multi-GPU design is documented but not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1505_00344_amd import api as A
+    from paper_1505_00344_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    w = I.wilson_cowan_4m(n=args.particles)
+    w.nsteps = args.rk4_steps
+    e = I.generate(w)
+    hs = w.hist
+    sysobj = A.System("wilson_cowan", 2, w.params)
+    stream = torch.cuda.current_stream()
+
+    def setup(prec):
+        dt_ = torch.float64 if prec == "fp64" else torch.float32
+        st = torch.as_tensor(e.state, dtype=dt_, device=dev).contiguous()
+        pp = torch.as_tensor(e.pparams, dtype=dt_, device=dev).contiguous()
+        comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+        hist = torch.zeros((hs["ny"], hs["nx"]), dtype=torch.int32, device=dev)
+        drop = torch.zeros(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(max(A.histogram_workspace_size(w.n, hs["nx"], hs["ny"]), 1), dtype=torch.uint8, device=dev)
+        return dict(st=st, pp=pp, comp=comp, hist=hist, drop=drop, ws=ws, prec=prec)
+
+    def one_step(B, ev=None):
+        # forward group, backward group, then the density grid
+        for k, (off, n, dt) in enumerate(zip(e.offsets, e.counts, e.dts)):
+            if ev is not None:
+                ev[k][0].record(stream)
+            A.integrate(sysobj, B["st"], dt, w.nsteps, n=n, offset=off, pparams=B["pp"], pp_slot=w.pp_slot,
+                        comp=B["comp"], prec=B["prec"])
+            if ev is not None:
+                ev[k][1].record(stream)
+        A.project_histogram(sysobj, B["st"], hs["axis_x"], hs["axis_y"], hs["x_range"], hs["y_range"], hs["nx"],
+                            hs["ny"], hist=B["hist"], n_dropped=B["drop"], pparams=B["pp"], pp_slot=w.pp_slot,
+                            prec="fp32" if B["prec"] != "fp64" else "fp64", workspace=B["ws"])
+
+    def measure(prec, steps, warmup):
+        B = setup(prec)
+        for _ in range(warmup):
+            one_step(B)
+        torch.cuda.synchronize()
+        evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in e.counts]
+               for _ in range(steps)]
+        t0 = time.perf_counter()
+        for s in range(steps):
+            one_step(B, evs[s])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = [ev[0].elapsed_time(ev[1]) for step in evs for ev in step]
+        return wall, kern_ms, B
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    wall, kern_ms, B = measure("fp32_kahan", args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    psteps = w.n * w.nsteps
+    value = psteps / (wall / args.steps)
+    avg_launch_ms = float(np.mean(kern_ms))
+    particles_per_launch = float(np.mean(e.counts))
+    flop_launch = particles_per_launch * w.nsteps * FLOP_PER_STEP["wilson_cowan"]["fp32_kahan"]
+    achieved = flop_launch / (avg_launch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32_kahan"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS["fp32_kahan"], 4), "traffic": None,
+            "kernel": "k_rk4<WilsonCowan<float>, Kahan>", "avg_launch_ms": round(avg_launch_ms, 4),
+            "flop_per_particle_step": FLOP_PER_STEP["wilson_cowan"]["fp32_kahan"],
+            "particles_per_launch": particles_per_launch, "steps_per_launch": w.nsteps}
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-RK4-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"wilson_cowan_4m: {w.n} particles (half h=+0.01, half h=-0.01), per-particle "
+                               f"P~U[-2,4], {w.nsteps} RK4 steps FP32-Kahan + {hs['nx']}x{hs['ny']} (P,E) grid",
+                   "precision": "fp32_kahan", "particles": w.n, "rk4_steps": w.nsteps},
+        "roofline": roof,
+    }
+    # FP64 beside it (same workload), reported, not the headline value
+    if not args.no_fp64:
+        wall64, kern64, B64 = measure("fp64", max(1, min(args.steps, 3)), 1)
+        v64 = psteps / (wall64 / max(1, min(args.steps, 3)))
+        a64 = particles_per_launch * w.nsteps * FLOP_PER_STEP["wilson_cowan"]["fp64"] / (np.mean(kern64) * 1e-3) / 1e12
+        out["fp64"] = {"value": v64, "unit": "particle-RK4-steps/s", "avg_launch_ms": round(float(np.mean(kern64)), 4),
+                       "achieved_tflops": round(a64, 3), "peak": PEAK_TFLOPS["fp64"],
+                       "frac": round(a64 / PEAK_TFLOPS["fp64"], 4)}
+        # accuracy of the measured FP32-comp state against FP64 on a sample
+        idx = np.arange(0, w.n, max(1, w.n // 65536))
+        s32 = B["st"][:, idx].double().cpu().numpy()
+        s64 = B64["st"][:, idx].cpu().numpy()
+        err = np.linalg.norm(s32 - s64, axis=0) / np.maximum(np.linalg.norm(s64, axis=0), 1.0)
+        fin = np.isfinite(err)
+        out["fp32_kahan_vs_fp64"] = {"median": float(np.median(err[fin])), "p99": float(np.quantile(err[fin], 0.99)),
+                                     "max": float(err[fin].max()), "sample": int(len(idx)),
+                                     "note": "same inputs; FP32 inputs/params/step rounded from FP64 differ, so "
+                                             "this includes input rounding; after %d steps of each run" %
+                                             (w.nsteps * (args.steps + args.warmup))}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(e, w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(e, w, seconds):
+    """Time the CPU oracle (FP64, OpenMP over particles, all host threads) on a
+    bounded sample of the same ensemble: every k-th particle of each group."""
+    import numpy as np
+
+    import oracle
+
+    oracle.lib()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+
+    def run(m):
+        t = 0.0
+        for off, n, dt in zip(e.offsets, e.counts, e.dts):
+            sel = np.arange(off, off + n)[:: max(1, n // m)][:m]
+            x = e.state[:, sel]
+            pp = e.pparams[:, sel]
+            t0 = time.perf_counter()
+            oracle.rk4(oracle.WILSON_COWAN, w.params, x, dt, w.nsteps, pp_slot=w.pp_slot, pparams=pp,
+                       nthreads=threads)
+            t += time.perf_counter() - t0
+        return t
+
+    m = 2048
+    t = run(m)
+    while t < seconds / 8 and m < min(e.counts):
+        m = min(m * 4, min(e.counts))
+        t = run(m)
+    m_final = min(int(m * seconds / max(t, 1e-3)), min(e.counts))
+    t = run(m_final)
+    total = m_final * len(e.counts)
+    return {"value": total * w.nsteps / t, "unit": "particle-RK4-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{total} of {w.n} particles (every k-th of each group), {w.nsteps} steps, FP64, "
+                      f"{t:.1f} s"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -19,7 +19,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libffo.so")
+# FFO_LIB points the wrapper at another build of ffo.cpp (the mutation test
+# uses it to load deliberately broken copies and check that the pins fail).
+LIB_PATH = os.environ.get("FFO_LIB") or os.path.join(HERE, "libffo.so")
 
 LINEAR, LORENZ, WILSON_COWAN, HH_RING, RICCATI = 0, 1, 2, 3, 100
 

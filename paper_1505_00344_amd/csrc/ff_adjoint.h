@@ -41,8 +41,10 @@ struct AdjArgs {
     void* lam;
     void* mu;
     double* mu_part;
+    void* carry;  // [NP][n] per-particle parameter adjoints carried between segments
     int64_t seg_len;
-    int first;
+    int first;    // first segment processed (the last in time): start from zero
+    int last;     // last segment processed (the first in time): write mu, mu_part
 };
 
 // Stage points of one step from x: y2 = x + (h/2)k1, y3 = x + (h/2)k2,
@@ -181,8 +183,9 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
     R* lm = static_cast<R*>(a.lam);
 #pragma unroll
     for (int d = 0; d < D; ++d) lam[d] = lm[d * a.ld + i];
+    R* carry = static_cast<R*>(a.carry);
 #pragma unroll
-    for (int q = 0; q < NP; ++q) gp[q] = R(0);
+    for (int q = 0; q < NP; ++q) gp[q] = a.first ? R(0) : carry[q * n + i];
     for (int64_t b = nsub - 1; b >= 0; --b) {
         const int64_t len = (L - b * T) < T ? (L - b * T) : T;
         R tape[T][D];
@@ -209,20 +212,25 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
     if (act) {
 #pragma unroll
         for (int d = 0; d < D; ++d) lm[d * a.ld + i] = lam[d];
-        R* mu = static_cast<R*>(a.mu);
+        if (!a.last) {
 #pragma unroll
-        for (int k = 0; k < kMaxPP; ++k) {
-            if (k < a.n_pp) {
-                R g = R(0);
+            for (int q = 0; q < NP; ++q) carry[q * n + i] = gp[q];
+        } else {
+            R* mu = static_cast<R*>(a.mu);
 #pragma unroll
-                for (int q = 0; q < NP; ++q)
-                    if (a.slot[k] == q) g = gp[q];
-                mu[k * a.ld + i] = a.first ? g : mu[k * a.ld + i] + g;
+            for (int k = 0; k < kMaxPP; ++k) {
+                if (k < a.n_pp) {
+                    R g = R(0);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q)
+                        if (a.slot[k] == q) g = gp[q];
+                    mu[k * a.ld + i] = g;
+                }
             }
         }
     }
     // per-block FP64 sums of every parameter adjoint, in a fixed order
-    if (a.mu_part) {
+    if (a.last && a.mu_part) {
         __shared__ double red[kAdjBlock / 64][kMaxParams];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -236,8 +244,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
         if (threadIdx.x < NP) {
             double s = 0.0;
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
-            double* mp = a.mu_part + (int64_t)blockIdx.x * kMaxParams + threadIdx.x;
-            *mp = a.first ? s : *mp + s;
+            a.mu_part[(int64_t)blockIdx.x * kMaxParams + threadIdx.x] = s;
         }
     }
 }
@@ -261,8 +268,10 @@ inline AdjArgs make_adj_args(const AdjLaunch& A) {
     a.lam = A.lam;
     a.mu = A.mu;
     a.mu_part = A.mu_part;
+    a.carry = A.carry;
     a.seg_len = A.seg_len;
     a.first = A.first;
+    a.last = A.last;
     return a;
 }
 

@@ -6,6 +6,9 @@
 //   ckpt_c [nseg][D][n]  its Kahan compensation (FF_FP32_KAHAN only)
 //   sub    [nsub][D][n]  sub-checkpoints inside one segment (T steps apart)
 //   sub_c  [nsub][D][n]  their compensation (FF_FP32_KAHAN only)
+//   carry  [NP][n]       per-particle adjoints of every parameter, carried
+//                        from one segment to the next (so the result does
+//                        not depend on K)
 //   mu_part [nblk][16]   FP64 per-block sums of the parameter adjoints
 // with nseg = ceil(nsteps / K), nsub = ceil(min(K, nsteps) / T) and
 // nblk = ceil(n / 256).
@@ -24,7 +27,7 @@ namespace {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct AdjLayout {
-    size_t ckpt, ckpt_c, sub, sub_c, mu_part, total;
+    size_t ckpt, ckpt_c, sub, sub_c, carry, mu_part, total;
     int64_t nseg, nsub, nblk;
 };
 
@@ -47,6 +50,8 @@ AdjLayout adj_layout(const ff_system_s* sys, const ff_batch* b, int64_t nsteps, 
     off += al((size_t)L.nsub * st);
     L.sub_c = off;
     if (kahan) off += al((size_t)L.nsub * st);
+    L.carry = off;
+    off += al((size_t)sys->n_params * (size_t)b->n * esz);
     L.mu_part = off;
     off += al((size_t)L.nblk * kMaxParams * sizeof(double));
     L.total = off;
@@ -168,11 +173,13 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
     A.lam = lambda;
     A.mu = mu;
     A.mu_part = (double*)(ws + W.mu_part);
+    A.carry = ws + W.carry;
     for (int64_t s = W.nseg - 1; s >= 0; --s) {
         A.ckpt = ws + W.ckpt + (size_t)s * stb;
         A.ckpt_c = b->prec == FF_FP32_KAHAN ? ws + W.ckpt_c + (size_t)s * stb : nullptr;
         A.seg_len = (nsteps - s * K) < K ? (nsteps - s * K) : K;
         A.first = s == W.nseg - 1;
+        A.last = s == 0;
         hipError_t e;
         switch (sys->rhs) {
             case FF_RHS_LINEAR: e = launch_adj_linear(sys->dim, A); break;

@@ -48,8 +48,10 @@ struct AdjLaunch {
     void* lam;           // adjoint of the state, SoA [dim][ld], in/out
     void* mu;            // per-particle parameter adjoints, SoA [n_pp][ld]
     double* mu_part;     // per-block FP64 partial sums of all parameter adjoints [nblk][kMaxParams]
+    void* carry;         // per-particle parameter adjoints between segments [NP][n]
     int64_t seg_len;     // steps in this segment
-    int first;           // 1 for the first segment processed (last in time): initialise mu, mu_part
+    int first;           // 1 for the first segment processed (last in time)
+    int last;            // 1 for the last segment processed (first in time)
 };
 
 // Steps held in registers by the adjoint's innermost recompute (per system).

@@ -1,0 +1,180 @@
+"""GPU parity of the checkpointed discrete adjoint (exact gradient of the RK4
+map of Section 2.1 / Appendix A.1) against the oracle's adjoint, the oracle's
+complex-step derivatives, central finite differences and closed forms."""
+import numpy as np
+import pytest
+
+import tolerances as tol
+from helpers import api, f32_inputs, quantiles, to_dev, to_host
+from paper_1505_00344_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def A():
+    return api()
+
+
+def rel(a, b, floor=tol.ADJ_FLOOR):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, nsteps, K, pp=None, pp_slot=(), dtype=torch.float64,
+                kahan=False, want_global=True):
+    sysobj = A.System(sysid, dim, params)
+    x = to_dev(x0, dtype)
+    ppt = None if pp is None else to_dev(pp, dtype)
+    comp = torch.zeros_like(x) if kahan else None
+    nbytes = A.adjoint_workspace_size(sysobj, x, nsteps, K, pparams=ppt, pp_slot=pp_slot, comp=comp)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda:0")
+    A.integrate_checkpointed(sysobj, x, dt, nsteps, K, ws, pparams=ppt, pp_slot=pp_slot, comp=comp)
+    lam = to_dev(lamT, dtype)
+    mu = None if ppt is None else torch.empty_like(ppt)
+    mug = torch.empty(len(params), dtype=torch.float64, device="cuda:0") if want_global else None
+    A.adjoint(sysobj, x, dt, nsteps, K, ws, lam, mu=mu, mu_global=mug, pparams=ppt, pp_slot=pp_slot,
+              prec="fp32_kahan" if kahan else None)
+    torch.cuda.synchronize()
+    return (to_host(x), to_host(lam), None if mu is None else to_host(mu),
+            None if mug is None else to_host(mug))
+
+
+def case(name, n):
+    if name == "lorenz":
+        w = I.lorenz_8m(n=n)
+        e = I.generate(w)
+        return I.LORENZ, 3, w.params, e.state, e.pparams, w.pp_slot, 0.005
+    if name == "wc_fwd":
+        w = I.wilson_cowan_4m(n=2 * n)
+        e = I.generate(w)
+        return I.WILSON_COWAN, 2, w.params, e.state[:, :n], e.pparams[:, :n], w.pp_slot, 0.01
+    if name == "wc_back":
+        w = I.wilson_cowan_4m(n=2 * n)
+        e = I.generate(w)
+        return I.WILSON_COWAN, 2, w.params, e.state[:, n:], e.pparams[:, n:], w.pp_slot, -0.01
+    if name == "hh":
+        w = I.hh_ring_1m(n=n)
+        e = I.generate(w)
+        return I.HH_RING, 15, w.params, e.state, e.pparams, w.pp_slot, 0.01
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name,n,nsteps,K", [("lorenz", 2000 + 17, 200, 50), ("lorenz", 999, 200, 37),
+                                             ("wc_fwd", 1500, 300, 64), ("wc_back", 1500, 300, 100),
+                                             ("hh", 300 + 5, 400, 100)])
+def test_fp64_adjoint_matches_oracle(A, ora, name, n, nsteps, K):
+    sysid, dim, params, x0, pp, slots, dt = case(name, n)
+    rng = np.random.default_rng(1)
+    lamT = rng.normal(size=x0.shape)
+    xT, lam0, mu, mug = gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, nsteps, K, pp, slots)
+    # forward state equals the plain run
+    ref_x = ora.rk4(sysid, params, x0, dt, nsteps, pp_slot=slots, pparams=pp)
+    fin = np.all(np.isfinite(ref_x), axis=0)
+    assert fin.all()
+    ref_l, ref_mu, ref_g = ora.adjoint(sysid, params, x0, lamT, dt, nsteps, pp_slot=slots, pparams=pp)
+    scale = np.abs(ref_l).max()
+    e_l = rel(lam0, ref_l, floor=tol.ADJ_FLOOR * max(scale, 1.0))
+    assert e_l.max() <= tol.ADJ_REL, quantiles(e_l)
+    e_mu = rel(mu, ref_mu, floor=tol.ADJ_FLOOR * max(np.abs(ref_mu).max(), 1.0))
+    assert e_mu.max() <= tol.ADJ_REL, quantiles(e_mu)
+    e_g = rel(mug, ref_g, floor=tol.ADJ_FLOOR * max(np.abs(ref_g).max(), 1.0))
+    assert e_g.max() <= tol.ADJ_REL, (mug, ref_g)
+
+
+def test_lorenz_dmean_z_dr_against_central_differences(A, ora):
+    # the bifurcation-diagram gradient: d(mean z(T))/d r_i over 200 steps with
+    # checkpoints every 50, against central differences with h = 1e-4 (FP64)
+    n = 4096
+    sysid, dim, params, x0, pp, slots, dt = case("lorenz", n)
+    lamT = np.zeros((3, n))
+    lamT[2] = 1.0 / n
+    _, _, mu, _ = gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, 200, 50, pp, slots)
+    sysobj = A.System(sysid, dim, params)
+    zs = []
+    for sgn in (1, -1):
+        x = to_dev(x0, torch.float64)
+        A.integrate(sysobj, x, dt, 200, pparams=to_dev(pp + sgn * 1e-4, torch.float64), pp_slot=slots)
+        zs.append(to_host(x)[2])
+    fd = (zs[0] - zs[1]) / 2e-4 / n
+    e = rel(mu[0], fd, floor=tol.ADJ_FLOOR / n)
+    assert np.quantile(e, 0.99) <= tol.ADJ_FD_P99 and e.max() <= tol.ADJ_FD_MAX, quantiles(e)
+    # and against the oracle's complex-step derivative, particle by particle
+    _, dxT = ora.rk4_cstep(sysid, params, x0, dt, 200, pp_slot=slots, pparams=pp, dpp=np.ones_like(pp))
+    e2 = rel(mu[0], dxT[2] / n, floor=tol.ADJ_FLOOR / n)
+    assert e2.max() <= tol.ADJ_REL, quantiles(e2)
+
+
+def test_linear_adjoint_closed_form(A):
+    rng = np.random.default_rng(5)
+    Am = rng.normal(size=(4, 4)) * 0.3
+    Z = 0.05 * Am
+    Z2 = Z @ Z
+    T = np.eye(4) + Z + Z2 / 2 + Z2 @ Z / 6 + Z2 @ Z2 / 24
+    x0 = rng.normal(size=(4, 700))
+    lamT = rng.normal(size=(4, 700))
+    _, lam0, _, _ = gpu_adjoint(A, I.LINEAR, 4, Am.ravel(), x0, lamT, 0.05, 100, 30)
+    want = np.linalg.matrix_power(T.T, 100) @ lamT
+    assert np.allclose(lam0, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("name", ["lorenz", "hh"])
+def test_adjoint_bitwise_independent_of_K(A, name):
+    n, nsteps = (1000, 120) if name == "lorenz" else (200, 60)
+    sysid, dim, params, x0, pp, slots, dt = case(name, n)
+    lamT = np.random.default_rng(2).normal(size=x0.shape)
+    outs = [gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, nsteps, K, pp, slots) for K in (nsteps, 7, 50)]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_kahan_adjoint_vs_fp64(A, ora):
+    # the single-precision compensated adjoint, reported against FP64
+    n = 3000
+    sysid, dim, params, x0, pp, slots, dt = case("lorenz", n)
+    x0 = f32_inputs(x0)
+    pp = f32_inputs(pp)
+    dt32 = float(np.float32(dt))
+    lamT = np.zeros((3, n))
+    lamT[2] = 1.0
+    _, _, mu32, mug32 = gpu_adjoint(A, sysid, dim, params, x0.astype(np.float32), lamT.astype(np.float32), dt32,
+                                    200, 50, pp.astype(np.float32), slots, dtype=torch.float32, kahan=True)
+    _, ref_mu, _ = ora.adjoint(sysid, params, x0, lamT, dt32, 200, pp_slot=slots, pparams=pp)
+    e = rel(mu32[0].astype(np.float64), ref_mu[0], floor=1e-3 * max(1.0, np.abs(ref_mu).max()))
+    assert np.quantile(e, 0.99) <= tol.ADJ_FP32_P99, quantiles(e)
+
+
+def test_autograd_function(A, ora):
+    from paper_1505_00344_amd.autograd import rk4_flow
+    n = 777
+    sysid, dim, params, x0, pp, slots, dt = case("wc_fwd", n)
+    sysobj = A.System(sysid, dim, params)
+    x = to_dev(x0, torch.float64).requires_grad_(True)
+    p = to_dev(pp, torch.float64).requires_grad_(True)
+    g = torch.tensor(params, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    xT = rk4_flow(x, sysobj, dt, 250, 40, pparams=p, pp_slot=slots, gparams=g)
+    loss = xT[0].sum() + 0.5 * (xT[1] ** 2).sum()
+    gx, gp, gg = torch.autograd.grad(loss, (x, p, g))
+    ref_xT = ora.rk4(sysid, params, x0, dt, 250, pp_slot=slots, pparams=pp)
+    assert np.array_equal(to_host(xT.detach()), ref_xT) or np.abs(to_host(xT.detach()) - ref_xT).max() < 1e-12
+    lamT = np.stack([np.ones(n), ref_xT[1]])
+    rl, rmu, rg = ora.adjoint(sysid, params, x0, lamT, dt, 250, pp_slot=slots, pparams=pp)
+    assert rel(to_host(gx), rl, floor=1e-3).max() <= 1e-9
+    assert rel(to_host(gp), rmu, floor=1e-3).max() <= 1e-9
+    assert rel(to_host(gg), rg, floor=1e-3 * np.abs(rg).max()).max() <= 1e-9
+
+
+def test_zero_steps_adjoint_is_identity(A):
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    x = torch.ones((3, 100), dtype=torch.float64, device="cuda:0")
+    lam = torch.arange(300, dtype=torch.float64, device="cuda:0").reshape(3, 100).contiguous()
+    lam0 = lam.clone()
+    pp = torch.full((1, 100), 28.0, dtype=torch.float64, device="cuda:0")
+    mu = torch.full((1, 100), 7.0, dtype=torch.float64, device="cuda:0")
+    mug = torch.full((3,), 7.0, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(1, dtype=torch.uint8, device="cuda:0")
+    A.adjoint(sysobj, x, 0.01, 0, 10, ws, lam, mu=mu, mu_global=mug, pparams=pp, pp_slot=[1])
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam0) and torch.count_nonzero(mu).item() == 0 and torch.count_nonzero(mug).item() == 0
