@@ -35,8 +35,14 @@ if ROOT not in sys.path:
 #   stage points 3 x 2 fma = 12; combination per component add + fma + add +
 #   fma = 6 -> 12.  Plain: 104.  Kahan update replaces the final fma (2) by
 #   mul, sub, add, sub, sub (5): +3 per component -> 110.
+#   Lorenz RHS: fx sub + mul (2), fy sub + fma (3), fz mul + fma (3) = 8,
+#   x4 = 32; stages 9 fma = 18; combination 3 x 6 = 18.  Plain 68, Kahan 77.
+#   Three-neuron HH ring, per neuron and evaluation: 67 (7 exp/expm1 and 4
+#   divisions counted once each), plus 1 for 1/C: 202 per evaluation, x4 =
+#   808; stages 15 fma = 90; combination 15 x 6 = 90.  Plain 988, Kahan 1033.
 FLOP_PER_STEP = {"wilson_cowan": {"fp32": 104, "fp32_kahan": 110, "fp64": 104},
-                 "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68}}
+                 "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68},
+                 "hh_ring": {"fp32": 988, "fp32_kahan": 1033, "fp64": 988}}
 PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
 METRIC = "particle-RK4-steps/s (FP32-comp vs FP64) + % VALU peak; adjoint steps/s"
 
@@ -51,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work for the baseline")
+    ap.add_argument("--extended", action="store_true",
+                    help="also measure the other workloads (Lorenz 8M, HH ring 1M, adjoints, mixed batch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -170,8 +178,168 @@ def main():
                                              (w.nsteps * (args.steps + args.warmup))}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(e, w, args.cpu_seconds)
+    if args.extended:
+        del B
+        if not args.no_fp64:
+            del B64
+        torch.cuda.empty_cache()
+        out["extended"] = extended(A, I, torch, np)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _time_stream(torch, fn, reps=1):
+    """Median over reps of fn()'s duration, HIP events on the current stream."""
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def extended(A, I, torch, np):
+    """Throughput of the other workloads (each run once after a warm-up)."""
+    dev = torch.device("cuda:0")
+    res = {}
+
+    def lorenz8m():
+        w = I.lorenz_8m()
+        e = I.generate(w)
+        sysobj = A.System("lorenz", 3, w.params)
+        r = {}
+        for prec in ("fp32", "fp32_kahan", "fp64"):
+            dt_ = torch.float64 if prec == "fp64" else torch.float32
+            st0 = torch.as_tensor(e.state, dtype=dt_, device=dev)
+            pp = torch.as_tensor(e.pparams, dtype=dt_, device=dev).contiguous()
+            st = st0.clone()
+            comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+            A.integrate(sysobj, st, 0.005, 20, pparams=pp, pp_slot=w.pp_slot, comp=comp, prec=prec)
+            ms = _time_stream(torch, lambda: A.integrate(sysobj, st, 0.005, w.nsteps, pparams=pp, pp_slot=w.pp_slot,
+                                                          comp=comp, prec=prec), reps=3)
+            ps = w.n * w.nsteps / (ms * 1e-3)
+            tf = ps * FLOP_PER_STEP["lorenz"][prec] / 1e12
+            r[prec] = {"particle_steps_per_s": ps, "ms": ms, "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[prec]}
+            # adjoint of mean z(T) w.r.t. each particle's r, 200 steps, K = 50
+            adj = w.adjoint
+            st = st0.clone()
+            comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+            nb = A.adjoint_workspace_size(sysobj, st, adj["nsteps"], adj["K"], pparams=pp, pp_slot=w.pp_slot, comp=comp,
+                                          prec=prec)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            lam = torch.zeros_like(st)
+            mu = torch.empty_like(pp)
+            mug = torch.empty(3, dtype=torch.float64, device=dev)
+            fwd = _time_stream(torch, lambda: A.integrate_checkpointed(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws,
+                                                                        pparams=pp, pp_slot=w.pp_slot, comp=comp,
+                                                                        prec=prec))
+
+            def back():
+                lam.zero_()
+                lam[2].fill_(1.0 / w.n)
+                A.adjoint(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws, lam, mu=mu, mu_global=mug, pparams=pp,
+                          pp_slot=w.pp_slot, prec=prec)
+            back()
+            bwd = _time_stream(torch, back, reps=3)
+            r[prec]["adjoint"] = {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
+                                  "adjoint_steps_per_s": w.n * adj["nsteps"] / (bwd * 1e-3),
+                                  "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3)}
+            del st, st0, pp, comp, ws, lam, mu
+        return r
+
+    def hh1m():
+        w = I.hh_ring_1m()
+        e = I.generate(w)
+        sysobj = A.System("hh_ring", 15, w.params)
+        r = {}
+        for prec in ("fp32_kahan", "fp64"):
+            dt_ = torch.float64 if prec == "fp64" else torch.float32
+            st0 = torch.as_tensor(e.state, dtype=dt_, device=dev)
+            pp = torch.as_tensor(e.pparams, dtype=dt_, device=dev).contiguous()
+            st = st0.clone()
+            comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+            A.integrate(sysobj, st, 0.01, 10, pparams=pp, pp_slot=w.pp_slot, comp=comp, prec=prec)
+            ms = _time_stream(torch, lambda: A.integrate(sysobj, st, 0.01, w.nsteps, pparams=pp, pp_slot=w.pp_slot,
+                                                          comp=comp, prec=prec))
+            ps = w.n * w.nsteps / (ms * 1e-3)
+            tf = ps * FLOP_PER_STEP["hh_ring"][prec] / 1e12
+            r[prec] = {"particle_steps_per_s": ps, "ms": ms, "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[prec]}
+            adj = w.adjoint
+            st = st0.clone()
+            comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+            nb = A.adjoint_workspace_size(sysobj, st, adj["nsteps"], adj["K"], pparams=pp, pp_slot=w.pp_slot, comp=comp,
+                                          prec=prec)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            lam = torch.zeros_like(st)
+            mu = torch.empty_like(pp)
+            fwd = _time_stream(torch, lambda: A.integrate_checkpointed(sysobj, st, 0.01, adj["nsteps"], adj["K"], ws,
+                                                                        pparams=pp, pp_slot=w.pp_slot, comp=comp,
+                                                                        prec=prec))
+            lam[0].fill_(1.0 / w.n)
+            bwd = _time_stream(torch, lambda: A.adjoint(sysobj, st, 0.01, adj["nsteps"], adj["K"], ws, lam, mu=mu,
+                                                        pparams=pp, pp_slot=w.pp_slot, prec=prec))
+            r[prec]["adjoint"] = {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
+                                  "adjoint_steps_per_s": w.n * adj["nsteps"] / (bwd * 1e-3),
+                                  "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3)}
+            del st, st0, pp, comp, ws, lam, mu
+        return r
+
+    def mixed():
+        ws_ = I.mixed_batch(1.0)
+        ens = I.generate_mixed(ws_)
+        names = {I.WILSON_COWAN: ("wilson_cowan", 2), I.LORENZ: ("lorenz", 3), I.HH_RING: ("hh_ring", 15)}
+        objs, specs = [], []
+        for w, e in zip(ws_, ens):
+            nm, dim = names[w.system]
+            sysobj = A.System(nm, dim, w.params)
+            st = torch.as_tensor(e.state, dtype=torch.float32, device=dev).contiguous()
+            pp = None if e.pparams is None else torch.as_tensor(e.pparams, dtype=torch.float32, device=dev).contiguous()
+            comp = torch.zeros_like(st)
+            objs.append((sysobj, st, pp, comp))
+            for off, n, dt in zip(e.offsets, e.counts, e.dts):
+                specs.append((sysobj, A.make_batch(st, n, pp, w.pp_slot, comp, "fp32_kahan", off), dt, w.pp_slot,
+                              st, pp, comp, off, n))
+        groups = A.make_groups([(s[0], s[1], s[2]) for s in specs])
+        nsteps = 200
+        t = A.autotune(groups, nsteps)
+        tun = (t.steps_per_launch, t.particles_per_thread, t.block)
+        gws = torch.empty(A.groups_workspace_size(len(groups)), dtype=torch.uint8, device=dev)
+        A.integrate_groups(groups, nsteps, tuning=tun, workspace=gws)
+        batched = _time_stream(torch, lambda: A.integrate_groups(groups, nsteps, tuning=tun, workspace=gws), reps=3)
+
+        def separate():
+            for s in specs:
+                A.integrate(s[0], s[4], s[2], nsteps, n=s[8], offset=s[7], pparams=s[5], pp_slot=s[3], comp=s[6],
+                            prec="fp32_kahan")
+        separate()
+        sep = _time_stream(torch, separate, reps=3)
+        # frame loop: one captured graph per frame, replayed 100 times
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            A.integrate_groups(groups, nsteps, tuning=tun, workspace=gws)
+        frames = []
+        for _ in range(100):
+            frames.append(_time_stream(torch, g.replay))
+        ntot = sum(s[8] for s in specs)
+        return {"particles": ntot, "groups": len(specs), "steps_per_frame": nsteps,
+                "autotuned": {"steps_per_launch": tun[0], "particles_per_thread": tun[1], "block": tun[2]},
+                "batched_ms": batched, "separate_ms": sep, "speedup_batched_vs_separate": sep / batched,
+                "particle_steps_per_s_batched": ntot * nsteps / (batched * 1e-3),
+                "frame_ms_p50": float(np.percentile(frames, 50)), "frame_ms_p99": float(np.percentile(frames, 99))}
+
+    for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed)):
+        try:
+            res[name] = fn()
+        except Exception as ex:  # report and continue with the next workload
+            res[name] = {"error": repr(ex)}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(e, w, seconds):

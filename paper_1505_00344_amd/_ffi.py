@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfireflies.so")
+# FF_LIB selects another build of the library (for A/B measurements).
+LIB_PATH = os.environ.get("FF_LIB") or os.path.join(HERE, "libfireflies.so")
 
 FF_OK, FF_E_INVALID, FF_E_UNSUPPORTED, FF_E_NOMEM, FF_E_DEVICE = range(5)
 FF_FP32, FF_FP32_KAHAN, FF_FP64 = 0, 1, 2

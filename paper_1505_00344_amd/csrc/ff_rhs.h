@@ -29,12 +29,26 @@ template <> struct M<double> {
     static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
 };
+// Single precision.  With FF_FAST_F32 the exponential is the hardware
+// 2^x (v_exp_f32) of x*log2(e) and reciprocals/divisions use v_rcp_f32 (each
+// about 1 ulp); expm1 stays the library function because psi(u) near u = 0
+// needs it.  Without it, every operation is the correctly rounded or
+// library-accurate one.
+#ifndef FF_FAST_F32
+#define FF_FAST_F32 0
+#endif
 template <> struct M<float> {
     static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+#if FF_FAST_F32
+    static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+#else
     static __device__ __forceinline__ float exp_(float x) { return expf(x); }
-    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
     static __device__ __forceinline__ float rcp_(float x) { return 1.0f / x; }
     static __device__ __forceinline__ float div_(float a, float b) { return a / b; }
+#endif
+    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
 };
 
 // ---------------------------------------------------------------- linear

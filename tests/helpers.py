@@ -1,7 +1,19 @@
 """Helpers shared by the GPU tests (no arithmetic of the method here)."""
+import json
+import os
+
 import numpy as np
 
 DEV = "cuda:0"
+
+
+def record(name, **values):
+    """Append measured error quantiles to the file named by FF_TEST_RECORD
+    (if set), one JSON object per line."""
+    path = os.environ.get("FF_TEST_RECORD")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": name, **values}) + "\n")
 
 
 def api():
