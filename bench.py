@@ -44,6 +44,38 @@ FLOP_PER_STEP = {"wilson_cowan": {"fp32": 104, "fp32_kahan": 110, "fp64": 104},
                  "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68},
                  "hh_ring": {"fp32": 988, "fp32_kahan": 1033, "fp64": 988}}
 PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
+# Sources that define the dominant kernel; the HBM traffic measured with
+# rocprofv3 counters is reported only while their hash matches the one
+# recorded next to the counters in profiles/.
+KERNEL_SOURCES = ["paper_1505_00344_amd/csrc/ff_rhs.h", "paper_1505_00344_amd/csrc/ff_rk4.h",
+                  "paper_1505_00344_amd/csrc/ff_internal.h", "paper_1505_00344_amd/csrc/k_rk4_wc.hip",
+                  "paper_1505_00344_amd/build.py"]
+COUNTERS_FILE = "profiles/wc4m_fp32kahan_hbm_counters.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """(bytes per launch, note) from the committed counter summary, or (None,
+    reason) when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, COUNTERS_FILE)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    vals = {}
+    for line in open(path):
+        if line.startswith("source_hash:") or line.startswith("traffic_bytes_per_launch:"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(vals["traffic_bytes_per_launch"]), COUNTERS_FILE
 METRIC = "particle-RK4-steps/s (FP32-comp vs FP64) + % VALU peak; adjoint steps/s"
 
 
@@ -143,8 +175,12 @@ def main():
     particles_per_launch = float(np.mean(e.counts))
     flop_launch = particles_per_launch * w.nsteps * FLOP_PER_STEP["wilson_cowan"]["fp32_kahan"]
     achieved = flop_launch / (avg_launch_ms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic()
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32_kahan"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS["fp32_kahan"], 4), "traffic": None,
+            "frac": round(achieved / PEAK_TFLOPS["fp32_kahan"], 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM read + write, calibrated rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+            "traffic_source": traffic_src,
+            "algorithmic_bytes_per_launch": particles_per_launch * 36,
             "kernel": "k_rk4<WilsonCowan<float>, Kahan>", "avg_launch_ms": round(avg_launch_ms, 4),
             "flop_per_particle_step": FLOP_PER_STEP["wilson_cowan"]["fp32_kahan"],
             "particles_per_launch": particles_per_launch, "steps_per_launch": w.nsteps}
@@ -159,8 +195,10 @@ def main():
     }
     # FP64 beside it (same workload), reported, not the headline value
     if not args.no_fp64:
-        wall64, kern64, B64 = measure("fp64", max(1, min(args.steps, 3)), 1)
-        v64 = psteps / (wall64 / max(1, min(args.steps, 3)))
+        # same number of passes as the FP32 run, so both states are compared
+        # after the same number of steps
+        wall64, kern64, B64 = measure("fp64", args.steps, args.warmup)
+        v64 = psteps / (wall64 / args.steps)
         a64 = particles_per_launch * w.nsteps * FLOP_PER_STEP["wilson_cowan"]["fp64"] / (np.mean(kern64) * 1e-3) / 1e12
         out["fp64"] = {"value": v64, "unit": "particle-RK4-steps/s", "avg_launch_ms": round(float(np.mean(kern64)), 4),
                        "achieved_tflops": round(a64, 3), "peak": PEAK_TFLOPS["fp64"],
@@ -173,9 +211,8 @@ def main():
         fin = np.isfinite(err)
         out["fp32_kahan_vs_fp64"] = {"median": float(np.median(err[fin])), "p99": float(np.quantile(err[fin], 0.99)),
                                      "max": float(err[fin].max()), "sample": int(len(idx)),
-                                     "note": "same inputs; FP32 inputs/params/step rounded from FP64 differ, so "
-                                             "this includes input rounding; after %d steps of each run" %
-                                             (w.nsteps * (args.steps + args.warmup))}
+                                     "note": "both runs from the same FP64 inputs (the FP32 run rounds them), after "
+                                             "%d RK4 steps each" % (w.nsteps * (args.steps + args.warmup))}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(e, w, args.cpu_seconds)
     if args.extended:

@@ -139,6 +139,41 @@ ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n
 ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
                        const ff_tuning* tuning, void* stream);
 
+/* The paper's reset rule (Section 2.1: a trajectory that leaves the region,
+ * or that has not been reset for more than a time T_max, restarts from new
+ * random initial conditions; Appendix A: the bounds of each state variable and
+ * the group's initial-condition box), applied on the device after every RK4
+ * step rather than lagged on the host (Appendix A.2):
+ *   age += 1; if some component x_d is outside [bound_lo[d], bound_hi[d]]
+ *   (NaN counts as outside) or age > max_age (max_age < 0: no age limit; the
+ *   paper's T_max in steps), the particle is redrawn uniformly in
+ *   [box_lo, box_hi), its Kahan compensation and age are set to 0 and
+ *   n_resets += 1.
+ * Draw number r (the particle's n_resets before the reset) of particle i uses
+ * Philox4x32-10 (Salmon et al., SC'11) with key (seed low 32 bits, seed high
+ * 32 bits) and counter (g low, g high, r, j), g = id_offset + i, block j:
+ *   FP64: component d takes words 2d, 2d+1 (a, b) of the stream,
+ *         u = ((a >> 5) * 2^26 + (b >> 6)) * 2^-53, x = fma(box_hi - box_lo, u, box_lo);
+ *   FP32: component d takes word d, u = (a >> 8) * 2^-24,
+ *         x = fmaf((float)(box_hi - box_lo), u, (float)box_lo).
+ * bound_* and box_* are host arrays of dim doubles; age (int32) and n_resets
+ * (uint32) are device arrays of n entries (particle i at index i), read and
+ * written.  Results are bitwise independent of the launch shape. */
+typedef struct {
+    const double* bound_lo;
+    const double* bound_hi;
+    const double* box_lo;
+    const double* box_hi;
+    int64_t max_age;
+    uint64_t seed;
+    uint64_t id_offset;
+    int32_t* age;
+    uint32_t* n_resets;
+} ff_reset;
+
+ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                             const ff_reset* reset, const ff_tuning* tuning, void* stream);
+
 /* 2D density projection (Appendix A "Render Technique", Appendix A.1:
  * additive accumulation of unit-weight points).  axis >= 0 selects state
  * component axis; axis = -1 - k selects per-particle parameter row k.  The

@@ -59,8 +59,19 @@ def lib():
         L.ffo_histogram.argtypes = [_int, _dp, _int, _dp, _i64, _i64, _int, _int,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, _int, _int, _u32p, _u64p, _int]
+        _u32a = ctypes.POINTER(ctypes.c_uint32)
+        _i32a = ctypes.POINTER(ctypes.c_int32)
+        L.ffo_philox4x32_10.argtypes = [_u32a, _u32a, _u32a]
+        L.ffo_rk4_reset.argtypes = [_int, _int, _dp, _int, _ip, _int, _dp, _dp, _i64, _i64,
+                                    ctypes.c_double, _i64, _dp, _dp, _dp, _dp, _i64,
+                                    ctypes.c_uint64, ctypes.c_uint64, _i32a, _u32a, _int]
+        L.ffo_rk4_reset_f32.argtypes = [_int, _int, _dp, _int, _ip, _int, _fp, _fp, _fp, _int,
+                                        _i64, _i64, ctypes.c_float, _i64, _dp, _dp, _dp, _dp,
+                                        _i64, ctypes.c_uint64, ctypes.c_uint64, _i32a, _u32a,
+                                        _int]
         for f in ("ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32",
-                  "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram"):
+                  "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram", "ffo_philox4x32_10",
+                  "ffo_rk4_reset", "ffo_rk4_reset_f32"):
             getattr(L, f).restype = _int
         _lib = L
     return _lib
@@ -198,3 +209,51 @@ def histogram(state, axis_x, axis_y, x_range, y_range, nx, ny, pparams=None,
                                float(y_range[1]), nx, ny, _ptr(h, _u32p), _ptr(d, _u64p),
                                int(acc)), "histogram")
     return h, int(d[0])
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of counter ctr[4] under key key[2] (uint32 words)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    _check(lib().ffo_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p)), "philox")
+    return out
+
+
+def rk4_reset(sys, params, state, h, nsteps, bounds, box, max_age=-1, seed=0, id_offset=0,
+              age=None, n_resets=None, pp_slot=None, pparams=None, prec="fp64", comp=None,
+              nthreads=0):
+    """RK4 with the reset rule; returns (state, comp, age, n_resets).
+
+    bounds, box: sequences of (lo, hi) per state component.  prec: "fp64",
+    "fp32" or "fp32_kahan" (state/pparams are then float32)."""
+    f64 = prec == "fp64"
+    st = (_f64(state) if f64 else _f32(state)).copy()
+    dim, n = st.shape
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64 if f64 else _f32)
+    blo = _f64([b[0] for b in bounds])
+    bhi = _f64([b[1] for b in bounds])
+    xlo = _f64([b[0] for b in box])
+    xhi = _f64([b[1] for b in box])
+    a = np.zeros(n, dtype=np.int32) if age is None else np.array(age, dtype=np.int32)
+    r = np.zeros(n, dtype=np.uint32) if n_resets is None else np.array(n_resets, dtype=np.uint32)
+    _i32p = ctypes.POINTER(ctypes.c_int32)
+    if f64:
+        _check(lib().ffo_rk4_reset(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp, _ptr(pp, _dp),
+                                   _ptr(st, _dp), n, n, float(h), int(nsteps), _ptr(blo, _dp),
+                                   _ptr(bhi, _dp), _ptr(xlo, _dp), _ptr(xhi, _dp), int(max_age),
+                                   int(seed), int(id_offset), _ptr(a, _i32p), _ptr(r, _u32p),
+                                   nthreads), "rk4_reset")
+        return st, None, a, r
+    kahan = prec == "fp32_kahan"
+    c = None
+    if kahan:
+        c = np.zeros_like(st) if comp is None else _f32(comp).copy()
+    _check(lib().ffo_rk4_reset_f32(sys, dim, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp, _ptr(pp, _fp),
+                                   _ptr(st, _fp), _ptr(c, _fp), int(kahan), n, n,
+                                   float(np.float32(h)), int(nsteps), _ptr(blo, _dp), _ptr(bhi, _dp),
+                                   _ptr(xlo, _dp), _ptr(xhi, _dp), int(max_age), int(seed),
+                                   int(id_offset), _ptr(a, _i32p), _ptr(r, _u32p), nthreads),
+           "rk4_reset_f32")
+    return st, c, a, r

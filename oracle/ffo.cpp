@@ -361,6 +361,65 @@ void particle_params(const double* params, int n_params, const int32_t* pp_slot,
 
 int threads_or_default(int nthreads) { return nthreads > 0 ? nthreads : omp_get_max_threads(); }
 
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 as defined by Salmon et al. (SC'11): ten rounds of
+//   (c0, c1, c2, c3) -> (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0))
+// with A = 0xD2511F53, B = 0xCD9E8D57, the key bumped by the Weyl constants
+// (0x9E3779B9, 0xBB67AE85) after every round but the last.
+void philox(const uint32_t in[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {in[0], in[1], in[2], in[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n1 = lo1, n2 = hi0 ^ c[3] ^ k1, n3 = lo0;
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+        if (round < 9) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+// Word w of the random stream of (particle g, draw r).
+uint32_t stream_word(uint64_t seed, uint64_t g, uint32_t r, int w) {
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), r, (uint32_t)(w / 4)};
+    uint32_t out[4];
+    philox(ctr, key, out);
+    return out[w % 4];
+}
+
+void redraw(int dim, const double* lo, const double* hi, uint64_t seed, uint64_t g, uint32_t r, double* x) {
+    for (int d = 0; d < dim; ++d) {
+        const uint32_t a = stream_word(seed, g, r, 2 * d), b = stream_word(seed, g, r, 2 * d + 1);
+        const double u = ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+        x[d] = std::fma(hi[d] - lo[d], u, lo[d]);
+    }
+}
+
+void redraw(int dim, const double* lo, const double* hi, uint64_t seed, uint64_t g, uint32_t r, float* x) {
+    for (int d = 0; d < dim; ++d) {
+        const uint32_t a = stream_word(seed, g, r, d);
+        const float u = (float)(a >> 8) * (1.0f / 16777216.0f);
+        x[d] = std::fma((float)(hi[d] - lo[d]), u, (float)lo[d]);
+    }
+}
+
+template <class T> bool escaped(int dim, const T* x, const double* blo, const double* bhi) {
+    for (int d = 0; d < dim; ++d) {
+        const double v = (double)x[d];
+        if (!(v >= blo[d] && v <= bhi[d])) return true;
+    }
+    return false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -521,6 +580,83 @@ int ffo_adjoint(int sys, int dim, const double* params, int n_params, const int3
             for (int64_t i = 0; i < n; ++i) acc += mu_all[static_cast<size_t>(i) * n_params + q];
             mu_global[q] = acc;
         }
+    }
+    return 0;
+}
+
+int ffo_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    philox(ctr, key, out);
+    return 0;
+}
+
+int ffo_rk4_reset(int sys, int dim, const double* params, int n_params, const int32_t* pp_slot,
+                  int n_pp, const double* pparams, double* state, int64_t n, int64_t ld, double h,
+                  int64_t nsteps, const double* bound_lo, const double* bound_hi,
+                  const double* box_lo, const double* box_hi, int64_t max_age, uint64_t seed,
+                  uint64_t id_offset, int32_t* age, uint32_t* n_resets, int nthreads) {
+    if (!valid_common(sys, dim, n_params, pp_slot, n_pp, n, ld) || nsteps < 0) return -1;
+    if (!bound_lo || !bound_hi || !box_lo || !box_hi || !age || !n_resets) return -1;
+    const double h2 = h * 0.5, h6 = h / 6.0;
+#pragma omp parallel for schedule(static) num_threads(threads_or_default(nthreads))
+    for (int64_t i = 0; i < n; ++i) {
+        double p[kMaxParams], x[kMaxDim];
+        particle_params(params, n_params, pp_slot, n_pp, pparams, ld, i, p);
+        for (int d = 0; d < dim; ++d) x[d] = state[d * ld + i];
+        int32_t a = age[i];
+        uint32_t r = n_resets[i];
+        for (int64_t s = 0; s < nsteps; ++s) {
+            rk4_step(sys, dim, p, x, h, h2, h6);
+            a += 1;
+            if (escaped(dim, x, bound_lo, bound_hi) || (max_age >= 0 && a > max_age)) {
+                redraw(dim, box_lo, box_hi, seed, id_offset + (uint64_t)i, r, x);
+                a = 0;
+                r += 1;
+            }
+        }
+        for (int d = 0; d < dim; ++d) state[d * ld + i] = x[d];
+        age[i] = a;
+        n_resets[i] = r;
+    }
+    return 0;
+}
+
+int ffo_rk4_reset_f32(int sys, int dim, const double* params, int n_params, const int32_t* pp_slot,
+                      int n_pp, const float* pparams, float* state, float* comp, int kahan,
+                      int64_t n, int64_t ld, float h, int64_t nsteps, const double* bound_lo,
+                      const double* bound_hi, const double* box_lo, const double* box_hi,
+                      int64_t max_age, uint64_t seed, uint64_t id_offset, int32_t* age,
+                      uint32_t* n_resets, int nthreads) {
+    if (!valid_common(sys, dim, n_params, pp_slot, n_pp, n, ld) || nsteps < 0) return -1;
+    if (!bound_lo || !bound_hi || !box_lo || !box_hi || !age || !n_resets) return -1;
+    if (kahan && comp == nullptr) return -1;
+    const float h2 = h * 0.5f, h6 = h / 6.0f;
+#pragma omp parallel for schedule(static) num_threads(threads_or_default(nthreads))
+    for (int64_t i = 0; i < n; ++i) {
+        float p[kMaxParams], x[kMaxDim], c[kMaxDim];
+        particle_params(params, n_params, pp_slot, n_pp, pparams, ld, i, p);
+        for (int d = 0; d < dim; ++d) {
+            x[d] = state[d * ld + i];
+            c[d] = kahan ? comp[d * ld + i] : 0.0f;
+        }
+        int32_t a = age[i];
+        uint32_t r = n_resets[i];
+        for (int64_t s = 0; s < nsteps; ++s) {
+            if (kahan) rk4_step_kahan(sys, dim, p, x, c, h, h2, h6);
+            else rk4_step(sys, dim, p, x, h, h2, h6);
+            a += 1;
+            if (escaped(dim, x, bound_lo, bound_hi) || (max_age >= 0 && a > max_age)) {
+                redraw(dim, box_lo, box_hi, seed, id_offset + (uint64_t)i, r, x);
+                for (int d = 0; d < dim; ++d) c[d] = 0.0f;
+                a = 0;
+                r += 1;
+            }
+        }
+        for (int d = 0; d < dim; ++d) {
+            state[d * ld + i] = x[d];
+            if (kahan) comp[d * ld + i] = c[d];
+        }
+        age[i] = a;
+        n_resets[i] = r;
     }
     return 0;
 }

@@ -102,6 +102,38 @@ int ffo_histogram(int dim, const double* state, int n_pp, const double* pparams,
                   int nx, int ny, uint32_t* hist, uint64_t* n_dropped,
                   int accumulate);
 
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11): out = the 10-round
+ * bijection of counter ctr[4] under key key[2]. */
+int ffo_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+/* RK4 with the paper's reset rule (Section 2.1: a trajectory that leaves the
+ * region, or that has not been reset for more than T_max, restarts from new
+ * random initial conditions; Appendix A: state-variable bounds and the
+ * group's initial-condition box).  After every step: age += 1; if a component
+ * is outside [bound_lo, bound_hi] (NaN counts as outside) or age > max_age
+ * (max_age < 0: never), the particle is redrawn uniformly in
+ * [box_lo, box_hi), age = 0 and n_resets += 1.  Draw number r (= n_resets
+ * before the reset) of particle g = id_offset + i uses Philox4x32-10 with key
+ * (seed low, seed high) and counter (g low, g high, r, j) for block j.
+ * FP64: component d takes words 2d, 2d+1 of the stream (a, b) and
+ * u = ((a >> 5) * 2^26 + (b >> 6)) * 2^-53; x = fma(box_hi - box_lo, u, box_lo).
+ * FP32: component d takes word d, u = (a >> 8) * 2^-24,
+ * x = fmaf((float)(box_hi - box_lo), u, (float)box_lo); a reset also zeroes
+ * the Kahan compensation.  age (int32) and n_resets (uint32) are [ld] arrays,
+ * carried in and out. */
+int ffo_rk4_reset(int sys, int dim, const double* params, int n_params, const int32_t* pp_slot,
+                  int n_pp, const double* pparams, double* state, int64_t n, int64_t ld, double h,
+                  int64_t nsteps, const double* bound_lo, const double* bound_hi,
+                  const double* box_lo, const double* box_hi, int64_t max_age, uint64_t seed,
+                  uint64_t id_offset, int32_t* age, uint32_t* n_resets, int nthreads);
+int ffo_rk4_reset_f32(int sys, int dim, const double* params, int n_params, const int32_t* pp_slot,
+                      int n_pp, const float* pparams, float* state, float* comp, int kahan,
+                      int64_t n, int64_t ld, float h, int64_t nsteps, const double* bound_lo,
+                      const double* bound_hi, const double* box_lo, const double* box_hi,
+                      int64_t max_age, uint64_t seed, uint64_t id_offset, int32_t* age,
+                      uint32_t* n_resets, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

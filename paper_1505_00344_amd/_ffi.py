@@ -36,6 +36,12 @@ class Tuning(_c.Structure):
     _fields_ = [("steps_per_launch", _i32), ("particles_per_thread", _i32), ("block", _i32)]
 
 
+class Reset(_c.Structure):
+    _fields_ = [("bound_lo", _c.POINTER(_dbl)), ("bound_hi", _c.POINTER(_dbl)), ("box_lo", _c.POINTER(_dbl)),
+                ("box_hi", _c.POINTER(_dbl)), ("max_age", _i64), ("seed", _c.c_uint64), ("id_offset", _c.c_uint64),
+                ("age", _vp), ("n_resets", _vp)]
+
+
 class Group(_c.Structure):
     _fields_ = [("sys", _vp), ("b", Batch), ("dt_signed", _dbl)]
 
@@ -50,6 +56,7 @@ SIGNATURES = {
     "ff_system_get_params": (_i32, [_vp, _c.POINTER(_dbl), _i32]),
     "ff_system_info": (_i32, [_vp, _c.POINTER(_i32), _c.POINTER(_i32), _c.POINTER(_i32)]),
     "ff_integrate": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Tuning), _vp]),
+    "ff_integrate_reset": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Reset), _c.POINTER(Tuning), _vp]),
     "ff_histogram_workspace_size": (_i32, [_i64, _i32, _i32, _c.POINTER(_sz)]),
     "ff_project_histogram": (_i32, [_vp, _c.POINTER(Batch), _i32, _i32, _dbl, _dbl, _dbl, _dbl,
                                     _i32, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),

@@ -127,6 +127,34 @@ def integrate(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, n=Non
          ctypes.byref(t) if t is not None else None, _stream(stream))
 
 
+def integrate_reset(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, bounds, box, age: torch.Tensor,
+                    n_resets: torch.Tensor, max_age: int = -1, seed: int = 0, id_offset: int = 0, n=None,
+                    pparams=None, pp_slot=(), comp=None, prec=None, tuning=None, stream=None, offset=0) -> None:
+    """ff_integrate_reset: RK4 with the reset rule.  bounds/box: (lo, hi) per
+    state component; age (int32) and n_resets (int32 storage of uint32
+    counts) are device tensors indexed like the particles of the slice
+    (``offset`` applies to them too)."""
+    b = make_batch(state, n, pparams, pp_slot, comp, prec, offset)
+    d = len(bounds)
+    arr = lambda v: (ctypes.c_double * d)(*map(float, v))
+    r = _ffi.Reset()
+    r.bound_lo = arr([x[0] for x in bounds])
+    r.bound_hi = arr([x[1] for x in bounds])
+    r.box_lo = arr([x[0] for x in box])
+    r.box_hi = arr([x[1] for x in box])
+    r.max_age = int(max_age)
+    r.seed = int(seed)
+    r.id_offset = int(id_offset)
+    for name, t in (("age", age), ("n_resets", n_resets)):
+        if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < offset + b.n:
+            raise ValueError(f"{name} must be a contiguous int32 tensor covering the particles")
+    r.age = age.data_ptr() + 4 * int(offset)
+    r.n_resets = n_resets.data_ptr() + 4 * int(offset)
+    t = make_tuning(tuning)
+    call("ff_integrate_reset", sys.handle, ctypes.byref(b), float(dt), int(nsteps), ctypes.byref(r),
+         ctypes.byref(t) if t is not None else None, _stream(stream))
+
+
 def histogram_workspace_size(n: int, nx: int, ny: int) -> int:
     out = ctypes.c_size_t()
     call("ff_histogram_workspace_size", int(n), int(nx), int(ny), ctypes.byref(out))

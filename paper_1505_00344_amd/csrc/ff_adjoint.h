@@ -50,15 +50,15 @@ struct AdjArgs {
 // Stage points of one step from x: y2 = x + (h/2)k1, y3 = x + (h/2)k2,
 // y4 = x + h k3 (stage s in 1..4; s = 1 returns x).
 template <class S, typename R>
-__device__ __forceinline__ void stage_point(const R (&p)[S::NP], const R (&x)[S::D], int s, R (&y)[S::D],
-                                            R h, R h2) {
+__device__ __forceinline__ void stage_point(const R (&p)[S::NP], const R (&q)[S::NQ], const R (&x)[S::D], int s,
+                                            R (&y)[S::D], R h, R h2) {
     constexpr int D = S::D;
     R k[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) y[d] = x[d];
 #pragma unroll 1
     for (int j = 1; j < s; ++j) {
-        S::f(p, y, k);
+        S::f(p, q, y, k);
         const R w = (j == 3) ? h : h2;
 #pragma unroll
         for (int d = 0; d < D; ++d) y[d] = M<R>::fma_(w, k[d], x[d]);
@@ -69,19 +69,19 @@ __device__ __forceinline__ void stage_point(const R (&p)[S::NP], const R (&x)[S:
 // (six right-hand sides instead of three) so that only one stage point is
 // live: the large systems would otherwise spill.
 template <class S, typename R, bool LOWREG>
-__device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&x)[S::D], R (&lam)[S::D],
-                                         R (&gp)[S::NP], R h, R h2, R h6, R h3) {
+__device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ], const R (&x)[S::D],
+                                         R (&lam)[S::D], R (&gp)[S::NP], R h, R h2, R h6, R h3) {
     constexpr int D = S::D;
     R ys[3][D];  // y2, y3, y4 when !LOWREG
     if constexpr (!LOWREG) {
         R k[D];
-        S::f(p, x, k);
+        S::f(p, q, x, k);
 #pragma unroll
         for (int d = 0; d < D; ++d) ys[0][d] = M<R>::fma_(h2, k[d], x[d]);
-        S::f(p, ys[0], k);
+        S::f(p, q, ys[0], k);
 #pragma unroll
         for (int d = 0; d < D; ++d) ys[1][d] = M<R>::fma_(h2, k[d], x[d]);
-        S::f(p, ys[1], k);
+        S::f(p, q, ys[1], k);
 #pragma unroll
         for (int d = 0; d < D; ++d) ys[2][d] = M<R>::fma_(h, k[d], x[d]);
     }
@@ -97,13 +97,13 @@ __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&x)[S::D]
 #pragma unroll
         for (int d = 0; d < D; ++d) g[d] = R(0);
         if (s == 1) {
-            S::vjp(p, x, a, g, gp);
+            S::vjp(p, q, x, a, g, gp);
         } else if constexpr (LOWREG) {
             R y[D];
-            stage_point<S, R>(p, x, s, y, h, h2);
-            S::vjp(p, y, a, g, gp);
+            stage_point<S, R>(p, q, x, s, y, h, h2);
+            S::vjp(p, q, y, a, g, gp);
         } else {
-            S::vjp(p, ys[s - 2], a, g, gp);
+            S::vjp(p, q, ys[s - 2], a, g, gp);
         }
         const R wg = (s == 4) ? h : h2;
         const R wl = (s == 2) ? h6 : h3;
@@ -151,6 +151,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
             p[q] = val;
         }
     }
+    R qd[S::NQ];
+    S::derive(p, qd);
     const R h = R(a.h), h2 = R(a.h2), h6 = R(a.h6), h3 = R(a.h3);
 
     const R* ck = static_cast<const R*>(a.ckpt);
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
             if (KAHAN) subc[b * D * n + d * n + i] = c[d];
         }
         if (b + 1 < nsub)
-            for (int t = 0; t < T; ++t) rk4_step<S, R, KAHAN>(p, x, c, h, h2, h6);
+            for (int t = 0; t < T; ++t) rk4_step<S, R, KAHAN>(p, qd, x, c, h, h2, h6);
     }
 
     // B. reverse sweep
@@ -199,14 +201,14 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
 #pragma unroll
         for (int t = 1; t < T; ++t) {
             if (t < len) {
-                rk4_step<S, R, KAHAN>(p, xs, cs, h, h2, h6);
+                rk4_step<S, R, KAHAN>(p, qd, xs, cs, h, h2, h6);
 #pragma unroll
                 for (int d = 0; d < D; ++d) tape[t][d] = xs[d];
             }
         }
 #pragma unroll
         for (int t = T - 1; t >= 0; --t) {
-            if (t < len) vjp_step<S, R, LOWREG>(p, tape[t], lam, gp, h, h2, h6, h3);
+            if (t < len) vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3);
         }
     }
     if (act) {

@@ -15,7 +15,8 @@
 // the tile index), then accumulates each tile in LDS and merges it into the
 // global grid with one atomic per non-zero bin per block:
 //   1. count:   bin of every particle -> binbuf; per-block tile counts; drops
-//   2. scan:    exclusive scan of the tile-major [tile][block] counts
+//   2. scan:    exclusive scan of each tile's per-block counts (one block
+//               per tile), then of the tile totals (one block)
 //   3. scatter: local bin index (uint16) of every kept particle -> its tile's
 //               segment of `sorted`
 //   4. accum:   block = (tile, chunk of <= 8192 entries): LDS histogram of
@@ -122,76 +123,86 @@ __global__ void __launch_bounds__(kBlock) k_hist_count(const R* ax, const R* ay,
     add_drops(dropped, drops, &s_drop);
 }
 
-// 2. scan (one block of 1024 threads): counts[t][b] -> exclusive prefix in
-// tile-major order; tile_start[t] = first entry of tile t (tile_start[ntiles]
-// = kept particles); chunk_start[t] = first accumulate block of tile t.
-__global__ void __launch_bounds__(1024) k_hist_scan(uint32_t* counts, int64_t entries, int nblk,
-                                                    int ntiles, uint32_t* tile_start,
-                                                    uint32_t* chunk_start) {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (entries + 1023) / 1024;
-    const int64_t lo = tid * per < entries ? tid * per : entries;
-    const int64_t hi = lo + per < entries ? lo + per : entries;
-    uint32_t sum = 0;
-    for (int64_t k = lo; k < hi; ++k) sum += counts[k];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+// Exclusive scan over a block of 1024 threads (16 wavefronts of 64):
+// returns the exclusive prefix of v and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
     }
-    uint32_t run = tid ? part[tid - 1] : 0u;
-    const uint32_t total = part[1023];
-    for (int64_t k = lo; k < hi; ++k) {
-        const uint32_t c = counts[k];
-        counts[k] = run;
-        run += c;
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+        uint32_t s = lane < 16 ? wsum[lane] : 0u;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t t = __shfl_up(s, off, 64);
+            if (lane >= off) s += t;
+        }
+        if (lane < 16) wsum[16 + lane] = s;  // inclusive scan of wave sums
     }
     __syncthreads();
-    // tile starts and accumulate-chunk starts (ntiles <= kMaxTiles)
-    __shared__ uint32_t nch[kMaxTiles];
-    for (int t = tid; t < ntiles; t += 1024) {
-        const uint32_t s0 = counts[(int64_t)t * nblk];
-        const uint32_t s1 = t + 1 < ntiles ? counts[(int64_t)(t + 1) * nblk] : total;
-        tile_start[t] = s0;
-        nch[t] = (uint32_t)((s1 - s0 + kAccChunk - 1) / kAccChunk);
-    }
-    if (tid == 0) tile_start[ntiles] = total;
+    const uint32_t before = wv ? wsum[16 + wv - 1] : 0u;
+    *total = wsum[16 + 15];
     __syncthreads();
-    // exclusive scan of nch over tiles: each thread owns 4 consecutive tiles
-    const int q = (ntiles + 1023) / 1024;
-    const int t0 = tid * q < ntiles ? tid * q : ntiles;
-    const int t1 = t0 + q < ntiles ? t0 + q : ntiles;
-    uint32_t s = 0;
-    for (int t = t0; t < t1; ++t) s += nch[t];
-    __syncthreads();
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    return before + inc - v;
+}
+
+// 2a. scan per tile (one block of 1024 threads per tile): counts[t][b] ->
+// exclusive prefix within tile t; tile_total[t] = kept particles of tile t.
+__global__ void __launch_bounds__(1024) k_hist_scan_tiles(uint32_t* counts, int nblk, uint32_t* tile_total) {
+    __shared__ uint32_t wsum[32];
+    uint32_t* row = counts + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblk; base += 1024) {
+        const int b = base + threadIdx.x;
+        const uint32_t v = b < nblk ? row[b] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan_1024(v, wsum, &tot);
+        if (b < nblk) row[b] = carry + ex;
+        carry += tot;
     }
-    uint32_t r = tid ? part[tid - 1] : 0u;
-    for (int t = t0; t < t1; ++t) {
-        const uint32_t c = nch[t];
-        chunk_start[t] = r;
-        r += c;
+    if (threadIdx.x == 0) tile_total[blockIdx.x] = carry;
+}
+
+// 2b. scan over tiles (one block of 1024 threads): tile_start[t] = first
+// entry of tile t in `sorted` (tile_start[ntiles] = kept particles);
+// chunk_start[t] = first accumulate block of tile t.
+__global__ void __launch_bounds__(1024) k_hist_scan_top(const uint32_t* tile_total, int ntiles, uint32_t* tile_start,
+                                                        uint32_t* chunk_start) {
+    __shared__ uint32_t wsum[32];
+    uint32_t carry = 0, ccarry = 0;
+    for (int base = 0; base < ntiles; base += 1024) {
+        const int t = base + threadIdx.x;
+        const uint32_t v = t < ntiles ? tile_total[t] : 0u;
+        const uint32_t c = (uint32_t)((v + kAccChunk - 1) / kAccChunk);
+        uint32_t tot, ctot;
+        const uint32_t ex = block_scan_1024(v, wsum, &tot);
+        const uint32_t cex = block_scan_1024(c, wsum, &ctot);
+        if (t < ntiles) {
+            tile_start[t] = carry + ex;
+            chunk_start[t] = ccarry + cex;
+        }
+        carry += tot;
+        ccarry += ctot;
     }
-    if (tid == 1023) chunk_start[ntiles] = part[1023];
+    if (threadIdx.x == 0) {
+        tile_start[ntiles] = carry;
+        chunk_start[ntiles] = ccarry;
+    }
 }
 
 // 3. scatter
 __global__ void __launch_bounds__(kBlock) k_hist_scatter(const uint32_t* binbuf, int64_t n, int ntiles,
-                                                         const uint32_t* offsets, uint16_t* sorted) {
+                                                         const uint32_t* offsets, const uint32_t* tile_start,
+                                                         uint16_t* sorted) {
     __shared__ uint32_t cur[kMaxTiles];
     const int nblk = gridDim.x;
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
-        cur[t] = offsets[(int64_t)t * nblk + blockIdx.x];
+        cur[t] = tile_start[t] + offsets[(int64_t)t * nblk + blockIdx.x];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kChunk;
     const int64_t hi = lo + kChunk < n ? lo + kChunk : n;
@@ -232,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_hist_accum(const uint16_t* sorted, i
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t binbuf, sorted, counts, tile_start, chunk_start, total;
+    size_t binbuf, sorted, counts, tile_total, tile_start, chunk_start, total;
 };
 
 WsLayout layout(int64_t n, int64_t nbins) {
@@ -247,6 +258,8 @@ WsLayout layout(int64_t n, int64_t nbins) {
     off += align256((size_t)n * 2);
     L.counts = off;
     off += align256((size_t)ntiles * (size_t)nblk * 4);
+    L.tile_total = off;
+    off += align256((size_t)ntiles * 4);
     L.tile_start = off;
     off += align256((size_t)(ntiles + 1) * 4);
     L.chunk_start = off;
@@ -315,15 +328,17 @@ hipError_t run_hist(const R* ax, const R* ay, int64_t n, const Geom& g, uint32_t
     uint32_t* binbuf = (uint32_t*)(ws + L.binbuf);
     uint16_t* sorted = (uint16_t*)(ws + L.sorted);
     uint32_t* counts = (uint32_t*)(ws + L.counts);
+    uint32_t* ttotal = (uint32_t*)(ws + L.tile_total);
     uint32_t* tstart = (uint32_t*)(ws + L.tile_start);
     uint32_t* cstart = (uint32_t*)(ws + L.chunk_start);
     hipLaunchKernelGGL((k_hist_count<R>), dim3(nblk), dim3(kBlock), 0, st, ax, ay, n, g, ntiles, binbuf, counts,
                        dropped);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(1024), 0, st, counts, (int64_t)ntiles * nblk, nblk, ntiles,
-                       tstart, cstart);
+    hipLaunchKernelGGL(k_hist_scan_tiles, dim3(ntiles), dim3(1024), 0, st, counts, nblk, ttotal);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_hist_scatter, dim3(nblk), dim3(kBlock), 0, st, binbuf, n, ntiles, counts, sorted);
+    hipLaunchKernelGGL(k_hist_scan_top, dim3(1), dim3(1024), 0, st, ttotal, ntiles, tstart, cstart);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(k_hist_scatter, dim3(nblk), dim3(kBlock), 0, st, binbuf, n, ntiles, counts, tstart, sorted);
     if (hipError_t e = hipGetLastError()) return e;
     const int64_t acc_blocks = (n + kAccChunk - 1) / kAccChunk + ntiles;
     hipLaunchKernelGGL(k_hist_accum, dim3((unsigned)acc_blocks), dim3(kBlock), 0, st, sorted, ntiles, tstart,

@@ -12,6 +12,8 @@ namespace ff {
 
 constexpr int kMaxParams = 16;
 constexpr int kMaxPP = FF_MAX_PP;
+constexpr int kMaxDim = 15;
+struct ResetArgs;
 
 struct ParamBlock {
     double v[kMaxParams];
@@ -35,6 +37,7 @@ struct RK4Launch {
     void* ckpt;          // if set: the launch first stores its starting state here
     void* ckpt_c;        //   (and the compensation here), SoA [dim][ckpt_ld]
     int64_t ckpt_ld;
+    const ResetArgs* reset;  // if set: apply the reset rule after every step
 };
 
 // Adjoint launch: one reverse segment of a checkpointed run.

@@ -3,8 +3,10 @@
 //
 // Each system is a struct template over the working precision R with
 //   D   number of state components,  NP  number of parameters,
-//   f(p, x, out)                 the right-hand side (autonomous: no t),
-//   vjp(p, x, a, gx, gp)         gx += J(x)^T a, gp += (df/dp)^T a.
+//   NQ  number of constants derived from the parameters once per particle,
+//   derive(p, q)                 fill q from p,
+//   f(p, q, x, out)              the right-hand side (autonomous: no t),
+//   vjp(p, q, x, a, gx, gp)      gx += J(x)^T a, gp += (df/dp)^T a.
 // Parameters live in a per-particle register array p[NP] (global values with
 // per-particle overrides already applied).
 //
@@ -23,28 +25,38 @@ namespace ff {
 // ---------------------------------------------------------------- math
 template <typename R> struct M;
 template <> struct M<double> {
+    static constexpr bool kFast = false;
     static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    // exp(x * c) for a compile-time constant c: the product is rounded, then exp
+    static __device__ __forceinline__ double expc(double x, double c) { return exp(x * c); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
 };
-// Single precision.  With FF_FAST_F32 the exponential is the hardware
-// 2^x (v_exp_f32) of x*log2(e) and reciprocals/divisions use v_rcp_f32 (each
-// about 1 ulp); expm1 stays the library function because psi(u) near u = 0
-// needs it.  Without it, every operation is the correctly rounded or
-// library-accurate one.
+// Single precision.  By default (FF_FAST_F32 = 1) the exponential is the
+// hardware 2^x (v_exp_f32) with log2(e) folded into the argument's scale, and
+// reciprocals/divisions use v_rcp_f32 (each about 1 ulp); expm1 stays the
+// library function because psi(u) near u = 0 needs it.  FF_FAST_F32 = 0 uses
+// the library expf and correctly rounded division instead.  Double precision
+// always uses the library exp/expm1 and correctly rounded division.
 #ifndef FF_FAST_F32
-#define FF_FAST_F32 0
+#define FF_FAST_F32 1
 #endif
+constexpr double kLog2e = 1.4426950408889634074;
 template <> struct M<float> {
+    static constexpr bool kFast = FF_FAST_F32 != 0;
     static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 #if FF_FAST_F32
-    static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * (float)kLog2e); }
+    static __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
+    static __device__ __forceinline__ float expc(float x, double c) { return __builtin_amdgcn_exp2f(x * (float)(c * kLog2e)); }
     static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 #else
     static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+    static __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
+    static __device__ __forceinline__ float expc(float x, double c) { return expf(x * (float)c); }
     static __device__ __forceinline__ float rcp_(float x) { return 1.0f / x; }
     static __device__ __forceinline__ float div_(float a, float b) { return a / b; }
 #endif
@@ -54,8 +66,9 @@ template <> struct M<float> {
 // ---------------------------------------------------------------- linear
 // x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.
 template <typename R, int Dm> struct Linear {
-    static constexpr int D = Dm, NP = Dm * Dm;
-    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+    static constexpr int D = Dm, NP = Dm * Dm, NQ = 1;
+    static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             R acc = p[r * D] * x[0];
@@ -64,8 +77,8 @@ template <typename R, int Dm> struct Linear {
             o[r] = acc;
         }
     }
-    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
-                                               R (&gx)[D], R (&gp)[NP]) {
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&)[NQ], const R (&x)[D],
+                                               const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
 #pragma unroll
         for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -79,16 +92,17 @@ template <typename R, int Dm> struct Linear {
 // ---------------------------------------------------------------- Lorenz
 // Section 2.2: x' = s (y - x), y' = x (r - z) - y, z' = x y - b z; p = [s, r, b].
 template <typename R> struct Lorenz {
-    static constexpr int D = 3, NP = 3;
-    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+    static constexpr int D = 3, NP = 3, NQ = 1;
+    static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
         o[0] = p[0] * (x[1] - x[0]);
         o[1] = M<R>::fma_(x[0], p[1] - x[2], -x[1]);
         o[2] = M<R>::fma_(x[0], x[1], -(p[2] * x[2]));
     }
     // J = [[-s, s, 0], [r - z, -1, -x], [y, x, -b]];  df/dp = diag-like
     // (y - x, x, -z) on (s, r, b).
-    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
-                                               R (&gx)[D], R (&gp)[NP]) {
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&)[NQ], const R (&x)[D],
+                                               const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         gx[0] += -p[0] * a[0] + (p[1] - x[2]) * a[1] + x[1] * a[2];
         gx[1] += p[0] * a[0] - a[1] + x[0] * a[2];
         gx[2] += -x[0] * a[1] - p[2] * a[2];
@@ -102,21 +116,28 @@ template <typename R> struct Lorenz {
 // E' = -E + S_E(c1 E - c2 I + P), I' = -I + S_I(c3 E - c4 I + Q),
 // S(u) = 1/(1 + exp(-a (u - th)));  p = [c1, c2, c3, c4, aE, thE, aI, thI, P, Q].
 template <typename R> struct WilsonCowan {
-    static constexpr int D = 2, NP = 10;
-    static __device__ __forceinline__ R sig(R a, R u, R th) {
-        return M<R>::rcp_(R(1) + M<R>::exp_(-(a * (u - th))));
+    static constexpr int D = 2, NP = 10, NQ = 2;
+    // fast single precision: q = -a*log2(e) per population, so that
+    // S = 1/(1 + 2^((u - th) * q)) costs one sub, mul, exp2, add and rcp
+    static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
+        q[0] = -p[4] * R(kLog2e);
+        q[1] = -p[6] * R(kLog2e);
     }
-    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+    static __device__ __forceinline__ R sig(R a, R qa, R u, R th) {
+        if constexpr (M<R>::kFast) return M<R>::rcp_(R(1) + M<R>::exp2_((u - th) * qa));
+        else return M<R>::rcp_(R(1) + M<R>::exp_(-(a * (u - th))));
+    }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R (&o)[D]) {
         const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
         const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-        o[0] = sig(p[4], uE, p[5]) - x[0];
-        o[1] = sig(p[6], uI, p[7]) - x[1];
+        o[0] = sig(p[4], q[0], uE, p[5]) - x[0];
+        o[1] = sig(p[6], q[1], uI, p[7]) - x[1];
     }
-    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
-                                               R (&gx)[D], R (&gp)[NP]) {
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D],
+                                               const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
         const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-        const R sE = sig(p[4], uE, p[5]), sI = sig(p[6], uI, p[7]);
+        const R sE = sig(p[4], q[0], uE, p[5]), sI = sig(p[6], q[1], uI, p[7]);
         const R qE = sE * (R(1) - sE), qI = sI * (R(1) - sI);
         const R dE = p[4] * qE * a[0];   // dS_E/du_E * a_E
         const R dI = p[6] * qI * a[1];
@@ -156,22 +177,23 @@ __device__ __forceinline__ R hh_psi(R u) {
 
 template <typename R>
 __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg) {
-    const R c10 = R(-1.0 / 10.0), c18 = R(-1.0 / 18.0), c20 = R(-1.0 / 20.0), c80 = R(-1.0 / 80.0);
+    const R c10 = R(-1.0 / 10.0);
     const R v65 = V + R(65.0);
     HHRate<R> q;
     q.am = hh_psi<R>((V + R(40.0)) * c10);
-    q.bm = R(4.0) * M<R>::exp_(v65 * c18);
-    q.ah = R(0.07) * M<R>::exp_(v65 * c20);
-    q.bh = M<R>::rcp_(R(1) + M<R>::exp_((V + R(35.0)) * c10));
+    q.bm = R(4.0) * M<R>::expc(v65, -1.0 / 18.0);
+    q.ah = R(0.07) * M<R>::expc(v65, -1.0 / 20.0);
+    q.bh = M<R>::rcp_(R(1) + M<R>::expc(V + R(35.0), -1.0 / 10.0));
     q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
-    q.bn = R(0.125) * M<R>::exp_(v65 * c80);
+    q.bn = R(0.125) * M<R>::expc(v65, -1.0 / 80.0);
     q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
     return q;
 }
 
 template <typename R, int N> struct HHRing {
-    static constexpr int D = 5 * N, NP = 14;
-    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&x)[D], R (&o)[D]) {
+    static constexpr int D = 5 * N, NP = 14, NQ = 1;
+    static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
         const R invC = M<R>::rcp_(p[6]);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -196,8 +218,8 @@ template <typename R, int N> struct HHRing {
         const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
         return (u == R(0)) ? R(-0.5) : d;
     }
-    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&x)[D], const R (&a)[D],
-                                               R (&gx)[D], R (&gp)[NP]) {
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&)[NQ], const R (&x)[D],
+                                               const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R invC = M<R>::rcp_(p[6]);
         const R th = p[12], sg = p[13];
 #pragma unroll

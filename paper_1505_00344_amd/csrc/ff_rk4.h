@@ -21,31 +21,32 @@
 #pragma once
 #include "ff_internal.h"
 #include "ff_rhs.h"
+#include "ff_rng.h"
 
 namespace ff {
 
 template <class S, typename R, bool KAHAN>
-__device__ __forceinline__ void rk4_step(const R (&p)[S::NP], R (&x)[S::D], R (&c)[S::D], R h, R h2,
-                                         R h6) {
+__device__ __forceinline__ void rk4_step(const R (&p)[S::NP], const R (&q)[S::NQ], R (&x)[S::D], R (&c)[S::D],
+                                         R h, R h2, R h6) {
     constexpr int D = S::D;
     R k1[D], k[D], y[D], acc[D];
-    S::f(p, x, k1);
+    S::f(p, q, x, k1);
 #pragma unroll
     for (int d = 0; d < D; ++d) y[d] = M<R>::fma_(h2, k1[d], x[d]);
-    S::f(p, y, k);
+    S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         y[d] = M<R>::fma_(h2, k[d], x[d]);
         acc[d] = k[d];
     }
-    S::f(p, y, k);
+    S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         y[d] = M<R>::fma_(h, k[d], x[d]);
         acc[d] = acc[d] + k[d];
         acc[d] = M<R>::fma_(R(2), acc[d], k1[d]);
     }
-    S::f(p, y, k);
+    S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         acc[d] = acc[d] + k[d];
@@ -76,6 +77,52 @@ struct RK4Args {
     int64_t ckpt_ld;
 };
 
+// The reset rule (Section 2.1): after every step a particle that left the
+// bounds (NaN counts as outside) or whose age exceeds max_age is redrawn
+// uniformly in its group's box from Philox4x32-10 (draw number = its reset
+// count, identity = id_offset + index), its compensation and age are zeroed.
+// FP64: u = ((a >> 5) * 2^26 + (b >> 6)) * 2^-53 from words 2d, 2d+1;
+// FP32: u = (a >> 8) * 2^-24 from word d; x = fma(width, u, lo).
+struct ResetArgs {
+    double blo[kMaxDim], bhi[kMaxDim];  // bounds, compared in double
+    double wd[kMaxDim], lod[kMaxDim];   // box width and low end (double)
+    float wf[kMaxDim], lof[kMaxDim];    // the same rounded to float
+    int64_t max_age;
+    uint64_t seed, id_offset;
+    int32_t* age;
+    uint32_t* nres;
+};
+
+template <typename R, int D>
+__device__ __forceinline__ bool escaped(const R (&x)[D], const ResetArgs& r) {
+    bool out = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double v = (double)x[d];
+        out = out || !(v >= r.blo[d] && v <= r.bhi[d]);
+    }
+    return out;
+}
+
+template <int D>
+__device__ __forceinline__ void redraw(double (&x)[D], const ResetArgs& r, uint64_t g, uint32_t k) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t a = draw_word(r.seed, g, k, 2 * d), b = draw_word(r.seed, g, k, 2 * d + 1);
+        const double u = ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+        x[d] = __builtin_fma(r.wd[d], u, r.lod[d]);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void redraw(float (&x)[D], const ResetArgs& r, uint64_t g, uint32_t k) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const float u = (float)(draw_word(r.seed, g, k, d) >> 8) * (1.0f / 16777216.0f);
+        x[d] = __builtin_fmaf(r.wf[d], u, r.lof[d]);
+    }
+}
+
 // Apply per-particle overrides with compile-time indices only, so the
 // parameter array stays in registers (no scratch).
 template <class S, typename R>
@@ -97,13 +144,13 @@ __device__ __forceinline__ void load_params(const RK4Args& a, int64_t i, R (&p)[
 // Advance the tile of blockDim*PPT particles starting at particle `first`.
 // Shared by the one-group launch (k_rk4) and the persistent ragged-batch
 // launch, so both produce the same bits.
-template <class S, typename R, bool KAHAN, int PPT>
-__device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first) {
+template <class S, typename R, bool KAHAN, int PPT, bool RESET = false>
+__device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const ResetArgs* rs = nullptr) {
     constexpr int D = S::D;
     R* st = static_cast<R*>(a.state);
     R* cp = static_cast<R*>(a.comp);
     const int64_t base = first + threadIdx.x;
-    R x[PPT][D], c[PPT][D], p[PPT][S::NP];
+    R x[PPT][D], c[PPT][D], p[PPT][S::NP], q[PPT][S::NQ];
     int64_t idx[PPT];
     bool act[PPT];
 #pragma unroll
@@ -112,6 +159,7 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first) {
         act[j] = i < a.n;
         idx[j] = act[j] ? i : a.n - 1;  // n >= 1: inactive lanes shadow a valid particle
         load_params<S, R>(a, idx[j], p[j]);
+        S::derive(p[j], q[j]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             x[j][d] = st[d * a.ld + idx[j]];
@@ -132,9 +180,38 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first) {
         }
     }
     const R h = R(a.h), h2 = R(a.h2), h6 = R(a.h6);
+    int32_t age[PPT];
+    uint32_t nres[PPT];
+    if constexpr (RESET) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            age[j] = rs->age[idx[j]];
+            nres[j] = rs->nres[idx[j]];
+        }
+    }
     for (int64_t s = 0; s < a.steps; ++s) {
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) rk4_step<S, R, KAHAN>(p[j], x[j], c[j], h, h2, h6);
+        for (int j = 0; j < PPT; ++j) {
+            rk4_step<S, R, KAHAN>(p[j], q[j], x[j], c[j], h, h2, h6);
+            if constexpr (RESET) {
+                age[j] += 1;
+                if (escaped<R, D>(x[j], *rs) || (rs->max_age >= 0 && age[j] > rs->max_age)) {
+                    redraw<D>(x[j], *rs, rs->id_offset + (uint64_t)idx[j], nres[j]);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) c[j][d] = R(0);
+                    age[j] = 0;
+                    nres[j] += 1;
+                }
+            }
+        }
+    }
+    if constexpr (RESET) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            if (!act[j]) continue;
+            rs->age[idx[j]] = age[j];
+            rs->nres[idx[j]] = nres[j];
+        }
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -150,6 +227,11 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first) {
 template <class S, typename R, bool KAHAN, int PPT>
 __global__ void __launch_bounds__(256) k_rk4(RK4Args a) {
     rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
+}
+
+template <class S, typename R, bool KAHAN, int PPT>
+__global__ void __launch_bounds__(256) k_rk4_reset(RK4Args a, ResetArgs r) {
+    rk4_tile<S, R, KAHAN, PPT, true>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT), &r);
 }
 
 inline RK4Args make_args(const RK4Launch& L) {
@@ -177,6 +259,14 @@ hipError_t launch_rk4_t(const RK4Launch& L) {
     const int64_t per_block = (int64_t)L.block * PPT;
     const int64_t grid = (L.n + per_block - 1) / per_block;
     if (grid <= 0) return hipSuccess;
+    if (L.reset) {
+        if constexpr (PPT <= 2) {
+            hipLaunchKernelGGL((k_rk4_reset<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
+                               make_args(L), *L.reset);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;  // the launcher clamps PPT to 2 for resets
+    }
     hipLaunchKernelGGL((k_rk4<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
                        make_args(L));
     return hipGetLastError();
@@ -186,7 +276,8 @@ hipError_t launch_rk4_t(const RK4Launch& L) {
 // clamped to MAXPPT).
 template <template <typename> class SysT, int MAXPPT>
 hipError_t dispatch_rk4(const RK4Launch& L) {
-    const int ppt = L.ppt > MAXPPT ? MAXPPT : L.ppt;
+    int ppt = L.ppt > MAXPPT ? MAXPPT : L.ppt;
+    if (L.reset && ppt > 2) ppt = 2;
     switch (L.prec) {
         case FF_FP64:
             if (ppt >= 4 && MAXPPT >= 4) return launch_rk4_t<SysT<double>, double, false, (MAXPPT >= 4 ? 4 : 1)>(L);
