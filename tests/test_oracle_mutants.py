@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "ffo.cpp")
 PINS = ["tests/test_oracle_tableau.py", "tests/test_oracle_linear.py", "tests/test_oracle_lorenz.py",
         "tests/test_oracle_wilson_cowan.py", "tests/test_oracle_hh.py", "tests/test_oracle_adjoint.py",
-        "tests/test_oracle_histogram.py"]
+        "tests/test_oracle_histogram.py", "tests/test_oracle_reset.py"]
 
 MUTANTS = {
     "rk4_weight": ("s = fma_(T(2), s, k1[d]);", "s = fma_(T(3), s, k1[d]);"),
@@ -37,6 +37,14 @@ MUTANTS = {
                        "const double Jl[9] = {-sigma, sigma, 0.0, r + Z, -1.0, -X, Y, X, -beta};"),
     "hist_edge": ("if (vx >= 0.0 && vx < nx && vy >= 0.0 && vy < ny) {", "if (vx >= 0.0 && vx <= nx && vy >= 0.0 && vy < ny) {"),
     "kahan_sign": ("c[d] = (t - x[d]) - yk;", "c[d] = (t - x[d]) + yk;"),
+    "philox_multiplier": ("const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];",
+                          "const uint64_t p1 = (uint64_t)0xCD9E8D55u * c[2];"),
+    "philox_key_bump": ("k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
+    "philox_rounds": ("for (int round = 0; round < 10; ++round) {", "for (int round = 0; round < 9; ++round) {"),
+    "reset_uniform_shift": ("((double)(a >> 5) * 67108864.0 + (double)(b >> 6))",
+                            "((double)(a >> 6) * 67108864.0 + (double)(b >> 6))"),
+    "reset_age_rule": ("if (escaped(dim, x, bound_lo, bound_hi) || (max_age >= 0 && a > max_age)) {\n                redraw(dim, box_lo, box_hi, seed, id_offset + (uint64_t)i, r, x);\n                a = 0;",
+                       "if (escaped(dim, x, bound_lo, bound_hi) || (max_age >= 0 && a >= max_age)) {\n                redraw(dim, box_lo, box_hi, seed, id_offset + (uint64_t)i, r, x);\n                a = 0;"),
 }
 
 
