@@ -174,6 +174,19 @@ typedef struct {
 ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
                              const ff_reset* reset, const ff_tuning* tuning, void* stream);
 
+/* Trajectory recording (Section 4 names it as future work: record a subset of
+ * trajectories, or all of them at an interval longer than the step).  Advances
+ * the batch like ff_integrate (or like ff_integrate_reset when `reset` is not
+ * NULL) and, after global steps every, 2*every, ..., stores the state of
+ * particles 0, stride, 2*stride, ... of the batch:
+ *   out[k][d][j] = component d of particle j*stride after step (k+1)*every,
+ * k = 0 .. nsteps/every - 1, j = 0 .. ceil(n/stride) - 1.  out: device array
+ * of the batch's element type, caller-owned, (nsteps/every)*dim*ceil(n/stride)
+ * elements.  The integration itself is bitwise that of ff_integrate. */
+ff_status ff_integrate_record(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                              int64_t every, int64_t stride, void* out, const ff_reset* reset,
+                              const ff_tuning* tuning, void* stream);
+
 /* 2D density projection (Appendix A "Render Technique", Appendix A.1:
  * additive accumulation of unit-weight points).  axis >= 0 selects state
  * component axis; axis = -1 - k selects per-particle parameter row k.  The
@@ -191,6 +204,40 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
                                double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
                                int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Particle image: the paper's render technique (Appendix A "Render
+ * Technique": 2D or perspective 3D projection onto chosen axes, colour fixed
+ * or varying linearly with position; Appendix A.1: model-view and
+ * view-projection transforms, a square sprite whose intensity falls off with
+ * the distance from its centre, additive blending GL_SRC_ALPHA/GL_ONE).  For
+ * each particle, with a = the three axis values (state component axis[i] >= 0
+ * or per-particle parameter -1 - axis[i]), all in double precision:
+ *   c = mvp (a0, a1, a2, 1), mvp row-major 4x4 = projection * view * model;
+ *   culled (counted in *n_culled) if c3 <= 0 or some c_i / c3 (i < 3) is
+ *   outside [-1, 1] or NaN; else px = (c0/c3 + 1) W/2, py = (1 - c1/c3) H/2;
+ *   rgb_k = min(max(base_k + sum_i grad[3k + i] (a_i - origin_i), 0), 1);
+ *   radius 0: pixel (floor px, floor py) gets w = weight; radius R > 0: every
+ *   pixel ix in floor(px - R - 1) .. floor(px + R + 1) (likewise iy) whose
+ *   centre is at distance d < R + 1 from (px, py) gets
+ *   w = weight (1 - d/(R + 1))^2;
+ *   img[(iy W + ix) 3 + k] += rint(256 * (w * rgb_k))  (pixels outside skipped).
+ * A 2D orthographic view is an mvp whose last row is (0, 0, 0, 1).  img:
+ * device uint32 [height][width][3], fixed point with 8 fractional bits, exact
+ * and independent of particle order; n_culled: device uint64 or NULL;
+ * accumulate == 0 clears both first.  radius <= 64. */
+typedef struct {
+    int32_t axis[3];
+    double mvp[16];
+    int32_t width, height;
+    double base[3];
+    double grad[9];
+    double origin[3];
+    double weight;
+    int32_t radius;
+} ff_render;
+
+ff_status ff_render_image(ff_system_t sys, const ff_batch* b, const ff_render* r, uint32_t* img,
+                          uint64_t* n_culled, int32_t accumulate, void* stream);
 
 /* Discrete adjoint (exact gradient of the RK4 map above with respect to the
  * initial state and the parameters; the Kahan update is differentiated as

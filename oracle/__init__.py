@@ -69,7 +69,9 @@ def lib():
                                         _i64, _i64, ctypes.c_float, _i64, _dp, _dp, _dp, _dp,
                                         _i64, ctypes.c_uint64, ctypes.c_uint64, _i32a, _u32a,
                                         _int]
-        for f in ("ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32",
+        L.ffo_render.argtypes = [_int, _dp, _int, _dp, _i64, _i64, ctypes.c_void_p, _u32p, _u64p,
+                                 _int]
+        for f in ("ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32", "ffo_render",
                   "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram", "ffo_philox4x32_10",
                   "ffo_rk4_reset", "ffo_rk4_reset_f32"):
             getattr(L, f).restype = _int
@@ -257,3 +259,43 @@ def rk4_reset(sys, params, state, h, nsteps, bounds, box, max_age=-1, seed=0, id
                                    int(id_offset), _ptr(a, _i32p), _ptr(r, _u32p), nthreads),
            "rk4_reset_f32")
     return st, c, a, r
+
+
+class RenderSpec(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int * 3), ("mvp", ctypes.c_double * 16), ("width", ctypes.c_int),
+                ("height", ctypes.c_int), ("base", ctypes.c_double * 3), ("grad", ctypes.c_double * 9),
+                ("origin", ctypes.c_double * 3), ("weight", ctypes.c_double), ("radius", ctypes.c_int)]
+
+
+def render_spec(axis, mvp, width, height, base=(1.0, 1.0, 1.0), grad=None, origin=(0.0, 0.0, 0.0),
+                weight=1.0, radius=0):
+    r = RenderSpec()
+    for i in range(3):
+        r.axis[i] = int(axis[i])
+    m = np.asarray(mvp, dtype=np.float64).reshape(16)
+    for i in range(16):
+        r.mvp[i] = float(m[i])
+    r.width, r.height = int(width), int(height)
+    g = np.zeros(9) if grad is None else np.asarray(grad, dtype=np.float64).reshape(9)
+    for i in range(3):
+        r.base[i] = float(base[i])
+        r.origin[i] = float(origin[i])
+    for i in range(9):
+        r.grad[i] = float(g[i])
+    r.weight = float(weight)
+    r.radius = int(radius)
+    return r
+
+
+def render(state, spec, pparams=None, img=None, n_culled=0):
+    """Particle image as fixed-point uint32 [H, W, 3]; returns (img, n_culled)."""
+    st = _f64(state)
+    dim, n = st.shape
+    pp = None if pparams is None else _f64(pparams).reshape(-1, n)
+    npp = 0 if pp is None else pp.shape[0]
+    acc = img is not None
+    im = np.zeros((spec.height, spec.width, 3), dtype=np.uint32) if img is None else np.array(img, dtype=np.uint32)
+    d = np.array([n_culled], dtype=np.uint64)
+    _check(lib().ffo_render(dim, _ptr(st, _dp), npp, _ptr(pp, _dp), n, n, ctypes.byref(spec),
+                            _ptr(im, _u32p), _ptr(d, _u64p), int(acc)), "render")
+    return im, int(d[0])

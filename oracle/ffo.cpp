@@ -691,3 +691,74 @@ int ffo_histogram(int dim, const double* state, int n_pp, const double* pparams,
 }
 
 }  // extern "C"
+
+extern "C" int ffo_render(int dim, const double* state, int n_pp, const double* pparams, int64_t n,
+                          int64_t ld, const ffo_render_t* r, uint32_t* img, uint64_t* n_culled,
+                          int accumulate) {
+    auto axis_ok = [&](int a) { return (a >= 0 && a < dim) || (a < 0 && -1 - a < n_pp); };
+    if (!r || !img || !n_culled || n < 0 || ld < n || r->width <= 0 || r->height <= 0 ||
+        r->radius < 0)
+        return -1;
+    for (int i = 0; i < 3; ++i)
+        if (!axis_ok(r->axis[i])) return -1;
+    const int64_t W = r->width, H = r->height;
+    if (!accumulate) {
+        std::fill(img, img + W * H * 3, 0u);
+        *n_culled = 0;
+    }
+    auto coord = [&](int a, int64_t i) {
+        return a >= 0 ? state[a * ld + i] : pparams[(-1 - a) * ld + i];
+    };
+    const double reach = r->radius + 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double a[3] = {coord(r->axis[0], i), coord(r->axis[1], i), coord(r->axis[2], i)};
+        double c[4];
+        for (int row = 0; row < 4; ++row) {
+            const double* m = r->mvp + 4 * row;
+            c[row] = m[0] * a[0] + m[1] * a[1] + m[2] * a[2] + m[3];
+        }
+        bool keep = c[3] > 0.0;
+        double ndc[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3 && keep; ++k) {
+            ndc[k] = c[k] / c[3];
+            keep = ndc[k] >= -1.0 && ndc[k] <= 1.0;
+        }
+        if (!keep) {
+            *n_culled += 1;
+            continue;
+        }
+        const double px = (ndc[0] + 1.0) * (double)W / 2.0;
+        const double py = (1.0 - ndc[1]) * (double)H / 2.0;
+        double rgb[3];
+        for (int k = 0; k < 3; ++k) {
+            double v = r->base[k];
+            for (int j = 0; j < 3; ++j) v += r->grad[3 * k + j] * (a[j] - r->origin[j]);
+            rgb[k] = std::min(std::max(v, 0.0), 1.0);
+        }
+        // radius 0: the pixel containing (px, py); radius R: every pixel whose
+        // centre lies closer than R + 1 to (px, py)
+        int64_t x0 = (int64_t)std::floor(px), x1 = x0, y0 = (int64_t)std::floor(py), y1 = y0;
+        if (r->radius > 0) {
+            x0 = (int64_t)std::floor(px - reach);
+            x1 = (int64_t)std::floor(px + reach);
+            y0 = (int64_t)std::floor(py - reach);
+            y1 = (int64_t)std::floor(py + reach);
+        }
+        for (int64_t iy = y0; iy <= y1; ++iy) {
+            for (int64_t ix = x0; ix <= x1; ++ix) {
+                if (ix < 0 || ix >= W || iy < 0 || iy >= H) continue;
+                double wgt = r->weight;
+                if (r->radius > 0) {
+                    const double dx = ((double)ix + 0.5) - px, dy = ((double)iy + 0.5) - py;
+                    const double d = std::sqrt(dx * dx + dy * dy);
+                    if (!(d < reach)) continue;
+                    const double f = 1.0 - d / reach;
+                    wgt = r->weight * (f * f);
+                }
+                for (int k = 0; k < 3; ++k)
+                    img[(iy * W + ix) * 3 + k] += (uint32_t)std::nearbyint(256.0 * (wgt * rgb[k]));
+            }
+        }
+    }
+    return 0;
+}

@@ -134,6 +134,34 @@ int ffo_rk4_reset_f32(int sys, int dim, const double* params, int n_params, cons
                       int64_t max_age, uint64_t seed, uint64_t id_offset, int32_t* age,
                       uint32_t* n_resets, int nthreads);
 
+/* Particle image (Appendix A "Render Technique"; Appendix A.1 vertex,
+ * geometry and fragment shaders with additive blending).  For each particle:
+ * the axis values a = (a0, a1, a2) (state component or per-particle parameter
+ * -1-k) form p = (a0, a1, a2, 1); c = M p with M the row-major 4x4
+ * projection * view * model matrix; the particle is culled if c3 <= 0 or a
+ * normalised coordinate c_i / c3 (i = 0, 1, 2) lies outside [-1, 1] or is
+ * NaN; otherwise its pixel position is px = (c0/c3 + 1) * W / 2,
+ * py = (1 - c1/c3) * H / 2.  Colour: rgb_k = min(max(base_k + sum_i
+ * grad[k][i] (a_i - origin_i), 0), 1).  Sprite: radius 0 gives
+ * w = weight to the pixel (floor(px), floor(py)); radius R > 0 gives every
+ * pixel (ix, iy) with floor(px - R - 1) <= ix <= floor(px + R + 1) (likewise
+ * iy) whose centre (ix + 0.5, iy + 0.5) lies at distance d < R + 1 from
+ * (px, py) the weight w = weight * (1 - d / (R + 1))^2.  Each such pixel receives w * rgb, added
+ * into img[(iy*W + ix)*3 + k] as the fixed-point integer
+ * nearbyint(256 * (w * rgb_k)) (pixels outside the image are skipped).  Everything is evaluated in double
+ * precision in the order written here; n_culled counts culled particles. */
+typedef struct {
+    int axis[3];
+    double mvp[16];
+    int width, height;
+    double base[3], grad[9], origin[3];
+    double weight;
+    int radius;
+} ffo_render_t;
+int ffo_render(int dim, const double* state, int n_pp, const double* pparams, int64_t n,
+               int64_t ld, const ffo_render_t* r, uint32_t* img, uint64_t* n_culled,
+               int accumulate);
+
 #ifdef __cplusplus
 }
 #endif

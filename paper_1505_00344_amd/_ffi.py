@@ -42,6 +42,11 @@ class Reset(_c.Structure):
                 ("age", _vp), ("n_resets", _vp)]
 
 
+class Render(_c.Structure):
+    _fields_ = [("axis", _i32 * 3), ("mvp", _dbl * 16), ("width", _i32), ("height", _i32), ("base", _dbl * 3),
+                ("grad", _dbl * 9), ("origin", _dbl * 3), ("weight", _dbl), ("radius", _i32)]
+
+
 class Group(_c.Structure):
     _fields_ = [("sys", _vp), ("b", Batch), ("dt_signed", _dbl)]
 
@@ -57,6 +62,9 @@ SIGNATURES = {
     "ff_system_info": (_i32, [_vp, _c.POINTER(_i32), _c.POINTER(_i32), _c.POINTER(_i32)]),
     "ff_integrate": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Tuning), _vp]),
     "ff_integrate_reset": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Reset), _c.POINTER(Tuning), _vp]),
+    "ff_integrate_record": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _i64, _i64, _vp, _c.POINTER(Reset),
+                                   _c.POINTER(Tuning), _vp]),
+    "ff_render_image": (_i32, [_vp, _c.POINTER(Batch), _c.POINTER(Render), _vp, _vp, _i32, _vp]),
     "ff_histogram_workspace_size": (_i32, [_i64, _i32, _i32, _c.POINTER(_sz)]),
     "ff_project_histogram": (_i32, [_vp, _c.POINTER(Batch), _i32, _i32, _dbl, _dbl, _dbl, _dbl,
                                     _i32, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),

@@ -127,14 +127,10 @@ def integrate(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, n=Non
          ctypes.byref(t) if t is not None else None, _stream(stream))
 
 
-def integrate_reset(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, bounds, box, age: torch.Tensor,
-                    n_resets: torch.Tensor, max_age: int = -1, seed: int = 0, id_offset: int = 0, n=None,
-                    pparams=None, pp_slot=(), comp=None, prec=None, tuning=None, stream=None, offset=0) -> None:
-    """ff_integrate_reset: RK4 with the reset rule.  bounds/box: (lo, hi) per
-    state component; age (int32) and n_resets (int32 storage of uint32
-    counts) are device tensors indexed like the particles of the slice
-    (``offset`` applies to them too)."""
-    b = make_batch(state, n, pparams, pp_slot, comp, prec, offset)
+def make_reset(bounds, box, age: torch.Tensor, n_resets: torch.Tensor, n: int, max_age: int = -1, seed: int = 0,
+               id_offset: int = 0, offset: int = 0):
+    """Describe the reset rule for the C ABI (host arrays are kept alive on
+    the returned object)."""
     d = len(bounds)
     arr = lambda v: (ctypes.c_double * d)(*map(float, v))
     r = _ffi.Reset()
@@ -150,9 +146,41 @@ def integrate_reset(sys: System, state: torch.Tensor, dt: float, nsteps: int, *,
             raise ValueError(f"{name} must be a contiguous int32 tensor covering the particles")
     r.age = age.data_ptr() + 4 * int(offset)
     r.n_resets = n_resets.data_ptr() + 4 * int(offset)
+    return r
+
+
+def integrate_reset(sys: System, state: torch.Tensor, dt: float, nsteps: int, *, bounds, box, age: torch.Tensor,
+                    n_resets: torch.Tensor, max_age: int = -1, seed: int = 0, id_offset: int = 0, n=None,
+                    pparams=None, pp_slot=(), comp=None, prec=None, tuning=None, stream=None, offset=0) -> None:
+    """ff_integrate_reset: RK4 with the reset rule.  bounds/box: (lo, hi) per
+    state component; age (int32) and n_resets (int32 storage of uint32
+    counts) are device tensors indexed like the particles of the slice
+    (``offset`` applies to them too)."""
+    b = make_batch(state, n, pparams, pp_slot, comp, prec, offset)
+    r = make_reset(bounds, box, age, n_resets, b.n, max_age, seed, id_offset, offset)
     t = make_tuning(tuning)
     call("ff_integrate_reset", sys.handle, ctypes.byref(b), float(dt), int(nsteps), ctypes.byref(r),
          ctypes.byref(t) if t is not None else None, _stream(stream))
+
+
+def integrate_record(sys: System, state: torch.Tensor, dt: float, nsteps: int, every: int, stride: int = 1, *,
+                     out: Optional[torch.Tensor] = None, reset: Optional[dict] = None, n=None, pparams=None,
+                     pp_slot=(), comp=None, prec=None, tuning=None, stream=None, offset=0) -> torch.Tensor:
+    """ff_integrate_record: returns out of shape (nsteps // every, dim,
+    ceil(n / stride)); ``reset`` (optional) holds make_reset's keywords."""
+    b = make_batch(state, n, pparams, pp_slot, comp, prec, offset)
+    m = (b.n + stride - 1) // stride if stride >= 1 else 0
+    shape = (int(nsteps) // int(every) if every >= 1 else 0, state.shape[0], m)
+    if out is None:
+        out = torch.empty(shape, dtype=state.dtype, device=state.device)
+    elif tuple(out.shape) != shape or out.dtype != state.dtype or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {state.dtype} tensor of shape {shape}")
+    r = None if reset is None else make_reset(n=b.n, offset=offset, **reset)
+    t = make_tuning(tuning)
+    call("ff_integrate_record", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(every), int(stride),
+         out.data_ptr() if out.numel() else None, ctypes.byref(r) if r is not None else None,
+         ctypes.byref(t) if t is not None else None, _stream(stream))
+    return out
 
 
 def histogram_workspace_size(n: int, nx: int, ny: int) -> int:
@@ -178,6 +206,37 @@ def project_histogram(sys: System, state: torch.Tensor, axis_x: int, axis_y: int
          float(x_range[0]), float(x_range[1]), float(y_range[0]), float(y_range[1]), int(nx), int(ny),
          hist.data_ptr(), n_dropped.data_ptr(), int(bool(accumulate)), ws_ptr, ws_bytes, _stream(stream))
     return hist, n_dropped
+
+
+def render_image(sys: System, state: torch.Tensor, axis, mvp, width: int, height: int, *, base=(1.0, 1.0, 1.0),
+                 grad=None, origin=(0.0, 0.0, 0.0), weight: float = 1.0, radius: int = 0,
+                 img: Optional[torch.Tensor] = None, n_culled: Optional[torch.Tensor] = None,
+                 accumulate: bool = False, n=None, pparams=None, pp_slot=(), prec=None, stream=None, offset=0):
+    """ff_render_image: returns (img int32 view of uint32 [H, W, 3] with 8
+    fractional bits, n_culled)."""
+    b = make_batch(state, n, pparams, pp_slot, None, prec if prec != "fp32_kahan" else "fp32", offset)
+    r = _ffi.Render()
+    for i in range(3):
+        r.axis[i] = int(axis[i])
+    m = [float(v) for row in mvp for v in row] if hasattr(mvp[0], "__len__") else [float(v) for v in mvp]
+    for i in range(16):
+        r.mvp[i] = m[i]
+    r.width, r.height = int(width), int(height)
+    g = [0.0] * 9 if grad is None else [float(v) for row in grad for v in row]
+    for i in range(3):
+        r.base[i] = float(base[i])
+        r.origin[i] = float(origin[i])
+    for i in range(9):
+        r.grad[i] = g[i]
+    r.weight = float(weight)
+    r.radius = int(radius)
+    if img is None:
+        img = torch.empty((int(height), int(width), 3), dtype=torch.int32, device=state.device)
+    if n_culled is None:
+        n_culled = torch.empty(1, dtype=torch.int64, device=state.device)
+    call("ff_render_image", sys.handle, ctypes.byref(b), ctypes.byref(r), img.data_ptr(), n_culled.data_ptr(),
+         int(bool(accumulate)), _stream(stream))
+    return img, n_culled
 
 
 def adjoint_workspace_size(sys: System, state: torch.Tensor, nsteps: int, K: int, *, n=None,

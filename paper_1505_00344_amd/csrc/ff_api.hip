@@ -221,15 +221,9 @@ ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int
 
 }  // extern "C"
 
-extern "C" ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
-                                        const ff_reset* reset, const ff_tuning* tuning, void* stream) {
-    g_error.clear();
-    if (ff_status s = check_system(sys)) return s;
-    if (ff_status s = check_batch(sys, b, true)) return s;
-    if (ff_status s = check_tuning(sys, tuning)) return s;
-    if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
-    if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
-    if (!reset) return fail(FF_E_INVALID, "reset is NULL");
+namespace ff {
+namespace {
+ff_status fill_reset(const ff_system_s* sys, const ff_batch* b, const ff_reset* reset, ResetArgs* r) {
     if (!reset->bound_lo || !reset->bound_hi || !reset->box_lo || !reset->box_hi)
         return fail(FF_E_INVALID, "reset bounds and box must be given");
     if (sys->dim > kMaxDim) return fail(FF_E_UNSUPPORTED, "reset supports up to 15 state variables");
@@ -240,30 +234,79 @@ extern "C" ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, doub
             return fail(FF_E_INVALID, "reset box must be finite with lo < hi");
     }
     if (b->n > 0 && (!reset->age || !reset->n_resets)) return fail(FF_E_INVALID, "reset age / n_resets are NULL");
-    if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
-    ResetArgs r;
-    std::memset(&r, 0, sizeof r);
+    std::memset(r, 0, sizeof *r);
     for (int d = 0; d < sys->dim; ++d) {
-        r.blo[d] = reset->bound_lo[d];
-        r.bhi[d] = reset->bound_hi[d];
-        r.wd[d] = reset->box_hi[d] - reset->box_lo[d];
-        r.lod[d] = reset->box_lo[d];
-        r.wf[d] = (float)r.wd[d];
-        r.lof[d] = (float)reset->box_lo[d];
+        r->blo[d] = reset->bound_lo[d];
+        r->bhi[d] = reset->bound_hi[d];
+        r->wd[d] = reset->box_hi[d] - reset->box_lo[d];
+        r->lod[d] = reset->box_lo[d];
+        r->wf[d] = (float)r->wd[d];
+        r->lof[d] = (float)reset->box_lo[d];
     }
-    r.max_age = reset->max_age;
-    r.seed = reset->seed;
-    r.id_offset = reset->id_offset;
-    r.age = reset->age;
-    r.nres = reset->n_resets;
-    const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
-    RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
-    L.reset = &r;
+    r->max_age = reset->max_age;
+    r->seed = reset->seed;
+    r->id_offset = reset->id_offset;
+    r->age = reset->age;
+    r->nres = reset->n_resets;
+    return FF_OK;
+}
+
+ff_status run_steps(const ff_system_s* sys, RK4Launch& L, int64_t nsteps, int64_t per_launch, const char* what) {
     for (int64_t done = 0; done < nsteps;) {
-        L.steps = nsteps - done < t.steps_per_launch ? nsteps - done : t.steps_per_launch;
+        L.steps = nsteps - done < per_launch ? nsteps - done : per_launch;
+        if (L.record) L.record->step0 = done;
         const hipError_t e = launch_rk4(sys, L);
-        if (e != hipSuccess) return device_fail(e, "ff_integrate_reset launch");
+        if (e != hipSuccess) return device_fail(e, what);
         done += L.steps;
     }
     return FF_OK;
+}
+}  // namespace
+}  // namespace ff
+
+extern "C" ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                                        const ff_reset* reset, const ff_tuning* tuning, void* stream) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (ff_status s = check_batch(sys, b, true)) return s;
+    if (ff_status s = check_tuning(sys, tuning)) return s;
+    if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
+    if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
+    if (!reset) return fail(FF_E_INVALID, "reset is NULL");
+    ResetArgs r;
+    if (ff_status s = fill_reset(sys, b, reset, &r)) return s;
+    if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
+    RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
+    L.reset = &r;
+    return run_steps(sys, L, nsteps, t.steps_per_launch, "ff_integrate_reset launch");
+}
+
+extern "C" ff_status ff_integrate_record(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
+                                         int64_t every, int64_t stride, void* out, const ff_reset* reset,
+                                         const ff_tuning* tuning, void* stream) {
+    g_error.clear();
+    if (ff_status s = check_system(sys)) return s;
+    if (ff_status s = check_batch(sys, b, true)) return s;
+    if (ff_status s = check_tuning(sys, tuning)) return s;
+    if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
+    if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
+    if (every < 1 || stride < 1) return fail(FF_E_INVALID, "every and stride must be >= 1");
+    if (b->n > 0 && nsteps >= every && !out) return fail(FF_E_INVALID, "out is NULL");
+    ResetArgs r;
+    if (reset) {
+        if (ff_status s = fill_reset(sys, b, reset, &r)) return s;
+    }
+    if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
+    RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
+    RecordArgs rc;
+    rc.out = out;
+    rc.every = every;
+    rc.stride = stride;
+    rc.m = (b->n + stride - 1) / stride;
+    rc.step0 = 0;
+    L.reset = reset ? &r : nullptr;
+    L.record = &rc;
+    return run_steps(sys, L, nsteps, t.steps_per_launch, "ff_integrate_record launch");
 }

@@ -14,6 +14,7 @@ constexpr int kMaxParams = 16;
 constexpr int kMaxPP = FF_MAX_PP;
 constexpr int kMaxDim = 15;
 struct ResetArgs;
+struct RecordArgs;
 
 struct ParamBlock {
     double v[kMaxParams];
@@ -38,6 +39,7 @@ struct RK4Launch {
     void* ckpt_c;        //   (and the compensation here), SoA [dim][ckpt_ld]
     int64_t ckpt_ld;
     const ResetArgs* reset;  // if set: apply the reset rule after every step
+    RecordArgs* record;      // if set: store every stride-th particle every `every` steps
 };
 
 // Adjoint launch: one reverse segment of a checkpointed run.

@@ -93,6 +93,14 @@ struct ResetArgs {
     uint32_t* nres;
 };
 
+// Trajectory recording: after global step g (1-based) with g % every == 0,
+// particle i with i % stride == 0 stores its state in
+// out[(g / every - 1)][d][i / stride] (m = recorded particles per record).
+struct RecordArgs {
+    void* out;
+    int64_t every, stride, m, step0;  // step0: global index of this launch's first step
+};
+
 template <typename R, int D>
 __device__ __forceinline__ bool escaped(const R (&x)[D], const ResetArgs& r) {
     bool out = false;
@@ -144,8 +152,9 @@ __device__ __forceinline__ void load_params(const RK4Args& a, int64_t i, R (&p)[
 // Advance the tile of blockDim*PPT particles starting at particle `first`.
 // Shared by the one-group launch (k_rk4) and the persistent ragged-batch
 // launch, so both produce the same bits.
-template <class S, typename R, bool KAHAN, int PPT, bool RESET = false>
-__device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const ResetArgs* rs = nullptr) {
+template <class S, typename R, bool KAHAN, int PPT, bool RESET = false, bool RECORD = false>
+__device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const ResetArgs* rs = nullptr,
+                                         const RecordArgs* rc = nullptr) {
     constexpr int D = S::D;
     R* st = static_cast<R*>(a.state);
     R* cp = static_cast<R*>(a.comp);
@@ -204,6 +213,20 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
                 }
             }
         }
+        if constexpr (RECORD) {
+            const int64_t g = rc->step0 + s + 1;
+            if (g % rc->every == 0) {
+                R* out = static_cast<R*>(rc->out) + (g / rc->every - 1) * D * rc->m;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (act[j] && idx[j] % rc->stride == 0) {
+                        const int64_t slot = idx[j] / rc->stride;
+#pragma unroll
+                        for (int d = 0; d < D; ++d) out[d * rc->m + slot] = x[j][d];
+                    }
+                }
+            }
+        }
     }
     if constexpr (RESET) {
 #pragma unroll
@@ -234,6 +257,12 @@ __global__ void __launch_bounds__(256) k_rk4_reset(RK4Args a, ResetArgs r) {
     rk4_tile<S, R, KAHAN, PPT, true>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT), &r);
 }
 
+template <class S, typename R, bool KAHAN, int PPT, bool RESET>
+__global__ void __launch_bounds__(256) k_rk4_record(RK4Args a, ResetArgs r, RecordArgs rc) {
+    rk4_tile<S, R, KAHAN, PPT, RESET, true>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT),
+                                            RESET ? &r : nullptr, &rc);
+}
+
 inline RK4Args make_args(const RK4Launch& L) {
     RK4Args a;
     a.state = L.state;
@@ -259,6 +288,19 @@ hipError_t launch_rk4_t(const RK4Launch& L) {
     const int64_t per_block = (int64_t)L.block * PPT;
     const int64_t grid = (L.n + per_block - 1) / per_block;
     if (grid <= 0) return hipSuccess;
+    if (L.record) {
+        if constexpr (PPT <= 2) {
+            const ResetArgs none{};
+            if (L.reset)
+                hipLaunchKernelGGL((k_rk4_record<S, R, KAHAN, PPT, true>), dim3((unsigned)grid), dim3(L.block), 0,
+                                   L.stream, make_args(L), *L.reset, *L.record);
+            else
+                hipLaunchKernelGGL((k_rk4_record<S, R, KAHAN, PPT, false>), dim3((unsigned)grid), dim3(L.block), 0,
+                                   L.stream, make_args(L), none, *L.record);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;  // the launcher clamps PPT to 2 for recording
+    }
     if (L.reset) {
         if constexpr (PPT <= 2) {
             hipLaunchKernelGGL((k_rk4_reset<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
@@ -277,7 +319,7 @@ hipError_t launch_rk4_t(const RK4Launch& L) {
 template <template <typename> class SysT, int MAXPPT>
 hipError_t dispatch_rk4(const RK4Launch& L) {
     int ppt = L.ppt > MAXPPT ? MAXPPT : L.ppt;
-    if (L.reset && ppt > 2) ppt = 2;
+    if ((L.reset || L.record) && ppt > 2) ppt = 2;
     switch (L.prec) {
         case FF_FP64:
             if (ppt >= 4 && MAXPPT >= 4) return launch_rk4_t<SysT<double>, double, false, (MAXPPT >= 4 ? 4 : 1)>(L);
