@@ -75,12 +75,15 @@ typedef enum {
  *                        is [V, m, h, n, s] at 5j and receives the synapse of
  *                        neuron (j - 1) mod N; dim 5 or 15 in this build;
  *                        params = [gNa, gK, gL, ENa, EK, EL, C, Iext, gsyn,
- *                        Esyn, r_rise, r_decay, theta_syn, sigma_syn]. */
+ *                        Esyn, r_rise, r_decay, theta_syn, sigma_syn].
+ *   FF_RHS_EXPR          a right-hand side given as expressions; made only by
+ *                        ff_system_create_expr, reported by ff_system_info. */
 typedef enum {
     FF_RHS_LINEAR = 0,
     FF_RHS_LORENZ = 1,
     FF_RHS_WILSON_COWAN = 2,
-    FF_RHS_HH_RING = 3
+    FF_RHS_HH_RING = 3,
+    FF_RHS_EXPR = 16
 } ff_rhs;
 
 typedef struct ff_system_s* ff_system_t; /* opaque, library-owned */
@@ -129,6 +132,50 @@ ff_status ff_system_destroy(ff_system_t sys);
 ff_status ff_system_set_params(ff_system_t sys, const double* params, int32_t n_params);
 ff_status ff_system_get_params(ff_system_t sys, double* params, int32_t n_params);
 ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n_params);
+
+/* A system whose right-hand side is given as text, one expression per state
+ * variable (Appendix A: a State Variable holds the expression of its time
+ * derivative; Appendix A.1: the step kernel is the general RK4 template with
+ * that right-hand side filled in, compiled at run time).  exprs[d] (host,
+ * NUL-terminated, copied) is x_d' over the names x0..x{dim-1} and
+ * p0..p{n_params-1}:
+ *   sum := product (('+'|'-') product)*   product := prefix (('*'|'/') prefix)*
+ *   prefix := '-' prefix | '+' prefix | atom
+ *   atom := number | name | func '(' sum (',' sum)* ')' | '(' sum ')'
+ * Binary operators associate to the left and a sign binds tighter than any of
+ * them.  A number starts with a digit or '.' and is read by strtod (decimal or
+ * hexadecimal, exponent allowed) into a double, which is then rounded to the
+ * working precision; names are x or p followed by an index without leading
+ * zeros; functions: exp expm1 log log1p sqrt sin cos tan tanh sinh cosh atan
+ * fabs (one argument), pow fmin fmax (two), fma (three: a*b+c rounded once).
+ * Every operation rounds to the working precision (no contraction, no fast
+ * math; the device math library's functions for the named functions).
+ * dim 1..15, n_params 0..16 (params: host array, copied; may be NULL when
+ * n_params == 0), at most 65536 characters per expression, 256 levels of
+ * nesting and 4096 distinct operations per system.  A syntax error returns
+ * FF_E_INVALID with the state variable, column and reason in ff_last_error().
+ * Nothing is compiled here: ff_integrate, ff_integrate_reset and
+ * ff_integrate_record compile the kernels of the batch's precision for the
+ * current device on first use (hipRTC; about a second) and keep them with the
+ * handle.  The adjoint and the ragged-batch calls (ff_integrate_groups,
+ * ff_autotune) hold compiled-in right-hand sides only and return
+ * FF_E_UNSUPPORTED for such a system. */
+ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n_params,
+                                const double* params, ff_system_t* out);
+
+/* Compile the kernels of an expression system for precision prec (ff_prec).
+ * arch == NULL: for the current device, and load them there (do this before
+ * capturing a stream into a graph, since the first integration of a
+ * precision otherwise compiles and loads during the call).  arch != NULL
+ * (e.g. "gfx950"): compile only, with no device needed (a check that the
+ * generated code builds).  FF_E_INVALID for a built-in system. */
+ff_status ff_system_compile(ff_system_t sys, int32_t prec, const char* arch);
+
+/* The generated kernel source of an expression system for precision prec:
+ * *len receives its size including the NUL; up to cap bytes are written to
+ * buf (NUL-terminated; FF_E_NOMEM if cap is too small; buf may be NULL to
+ * ask for the size). */
+ff_status ff_system_source(ff_system_t sys, int32_t prec, char* buf, size_t cap, size_t* len);
 
 /* Advance every particle of the batch by nsteps classical RK4 steps of size
  * dt_signed (Section 2.1; Appendix A.1-A.2).  In single precision the step is

@@ -71,7 +71,13 @@ def lib():
                                         _int]
         L.ffo_render.argtypes = [_int, _dp, _int, _dp, _i64, _i64, ctypes.c_void_p, _u32p, _u64p,
                                  _int]
-        for f in ("ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32", "ffo_render",
+        _cpp = ctypes.POINTER(ctypes.c_char_p)
+        L.ffo_expr_rk4.argtypes = [_int, _cpp, _dp, _int, _ip, _int, _dp, _dp, _i64, _i64,
+                                   ctypes.c_double, _i64]
+        L.ffo_expr_rk4_f32.argtypes = [_int, _cpp, _dp, _int, _ip, _int, _fp, _fp, _fp, _i64,
+                                       _i64, ctypes.c_float, _i64]
+        L.ffo_expr_error.restype = ctypes.c_char_p
+        for f in ("ffo_expr_rk4", "ffo_expr_rk4_f32", "ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32", "ffo_render",
                   "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram", "ffo_philox4x32_10",
                   "ffo_rk4_reset", "ffo_rk4_reset_f32"):
             getattr(L, f).restype = _int
@@ -299,3 +305,48 @@ def render(state, spec, pparams=None, img=None, n_culled=0):
     _check(lib().ffo_render(dim, _ptr(st, _dp), npp, _ptr(pp, _dp), n, n, ctypes.byref(spec),
                             _ptr(im, _u32p), _ptr(d, _u64p), int(acc)), "render")
     return im, int(d[0])
+
+
+def _exprs(exprs):
+    arr = (ctypes.c_char_p * len(exprs))(*[e.encode() for e in exprs])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p)), arr
+
+
+def _expr_check(rc):
+    if rc == -2:
+        raise ValueError("oracle expr_rk4: " + lib().ffo_expr_error().decode())
+    _check(rc, "expr_rk4")
+
+
+def expr_rk4(exprs, params, state, h, nsteps, pp_slot=None, pparams=None):
+    """FP64 RK4 of the system x_d' = exprs[d] (names x0.., p0..); returns the final state."""
+    st = _f64(state).copy()
+    dim, n = st.shape
+    if len(exprs) != dim:
+        raise ValueError("one expression per state variable")
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64)
+    ex, _keep = _exprs(exprs)
+    _expr_check(lib().ffo_expr_rk4(dim, ex, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                                   _ptr(pp, _dp), _ptr(st, _dp), n, n, float(h), int(nsteps)))
+    return st
+
+
+def expr_rk4_f32(exprs, params, state, h, nsteps, pp_slot=None, pparams=None, kahan=False,
+                 comp=None):
+    """Single-precision form of :func:`expr_rk4` (params and literals rounded to
+    float); returns (state, comp)."""
+    st = _f32(state).copy()
+    dim, n = st.shape
+    if len(exprs) != dim:
+        raise ValueError("one expression per state variable")
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f32)
+    c = None
+    if kahan:
+        c = np.zeros_like(st) if comp is None else _f32(comp).copy()
+    ex, _keep = _exprs(exprs)
+    _expr_check(lib().ffo_expr_rk4_f32(dim, ex, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                                       _ptr(pp, _fp), _ptr(st, _fp), _ptr(c, _fp), n, n,
+                                       float(np.float32(h)), int(nsteps)))
+    return st, c

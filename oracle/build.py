@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libffo.so")
-SRC = os.path.join(HERE, "ffo.cpp")
+SRCS = [os.path.join(HERE, "ffo.cpp"), os.path.join(HERE, "ffo_expr.cpp")]
 
 FLAGS = ["-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
          "-fPIC", "-shared", "-Wall", "-Wextra"]
@@ -18,7 +18,7 @@ FLAGS = ["-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["g++", *FLAGS, SRC, "-o", tmp]
+    cmd = ["g++", *FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -162,6 +162,22 @@ int ffo_render(int dim, const double* state, int n_pp, const double* pparams, in
                int64_t ld, const ffo_render_t* r, uint32_t* img, uint64_t* n_culled,
                int accumulate);
 
+/* User right-hand sides given as expressions (Appendix A: one expression per
+ * state variable; Appendix A.1: turned into the step kernel).  exprs[d] is the
+ * expression of x_d' over x0..x{dim-1} and p0..p{n_params-1} (grammar in
+ * ffo_expr.cpp), evaluated as written, left to right, every operation
+ * rounded to the working precision (double, or float for the _f32 form,
+ * where comp != NULL selects the Kahan-compensated update).  dim <= 16,
+ * n_params <= 32, n_pp <= 4.  Returns -1 for bad sizes, -2 with
+ * ffo_expr_error() set when an expression does not parse. */
+int ffo_expr_rk4(int dim, const char* const* exprs, const double* params, int n_params,
+                 const int32_t* pp_slot, int n_pp, const double* pparams, double* state,
+                 int64_t n, int64_t ld, double h, int64_t nsteps);
+int ffo_expr_rk4_f32(int dim, const char* const* exprs, const double* params, int n_params,
+                     const int32_t* pp_slot, int n_pp, const float* pparams, float* state,
+                     float* comp, int64_t n, int64_t ld, float h, int64_t nsteps);
+const char* ffo_expr_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _ffi
-from ._ffi import (FF_FP32, FF_FP32_KAHAN, FF_FP64, FF_RHS_HH_RING, FF_RHS_LINEAR,
+from ._ffi import (FF_FP32, FF_FP32_KAHAN, FF_FP64, FF_RHS_EXPR, FF_RHS_HH_RING, FF_RHS_LINEAR,
                    FF_RHS_LORENZ, FF_RHS_WILSON_COWAN, Batch, Group, Tuning, call)
 
 RHS = {"linear": FF_RHS_LINEAR, "lorenz": FF_RHS_LORENZ, "wilson_cowan": FF_RHS_WILSON_COWAN,
@@ -42,6 +42,34 @@ class System:
         call("ff_system_create", self.rhs, self.dim, len(params), p, ctypes.byref(h))
         self.handle = h
         self.n_params = len(params)
+
+    @classmethod
+    def from_exprs(cls, exprs: Sequence[str], params: Sequence[float] = ()) -> "System":
+        """A system whose right-hand side is given as text (ff_system_create_expr):
+        ``exprs[d]`` is x_d' over ``x0..`` and ``p0..``."""
+        self = cls.__new__(cls)
+        arr = (ctypes.c_char_p * len(exprs))(*[e.encode() for e in exprs])
+        p = (ctypes.c_double * max(len(params), 1))(*map(float, params))
+        h = ctypes.c_void_p()
+        call("ff_system_create_expr", len(exprs), arr, len(params), p, ctypes.byref(h))
+        self.handle = h
+        self.rhs = FF_RHS_EXPR
+        self.dim = len(exprs)
+        self.n_params = len(params)
+        self.exprs = list(exprs)
+        return self
+
+    def compile(self, prec: str = "fp64", arch: Optional[str] = None) -> None:
+        """Compile (and, without ``arch``, load) the kernels of one precision."""
+        call("ff_system_compile", self.handle, PREC[prec], None if arch is None else arch.encode())
+
+    def source(self, prec: str = "fp64") -> str:
+        """The generated kernel source of an expression system."""
+        n = ctypes.c_size_t()
+        call("ff_system_source", self.handle, PREC[prec], None, 0, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        call("ff_system_source", self.handle, PREC[prec], buf, n.value, ctypes.byref(n))
+        return buf.value.decode()
 
     def set_params(self, params: Sequence[float]) -> None:
         p = (ctypes.c_double * len(params))(*map(float, params))
@@ -142,7 +170,7 @@ def make_reset(bounds, box, age: torch.Tensor, n_resets: torch.Tensor, n: int, m
     r.seed = int(seed)
     r.id_offset = int(id_offset)
     for name, t in (("age", age), ("n_resets", n_resets)):
-        if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < offset + b.n:
+        if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < offset + int(n):
             raise ValueError(f"{name} must be a contiguous int32 tensor covering the particles")
     r.age = age.data_ptr() + 4 * int(offset)
     r.n_resets = n_resets.data_ptr() + 4 * int(offset)

@@ -87,6 +87,8 @@ hipError_t zero_async(void* p, int64_t bytes, hipStream_t st) {
 
 ff_status check_adj_args(const ff_system_s* sys, const ff_batch* b, double dt, int64_t nsteps, int32_t K) {
     if (ff_status s = check_system(sys)) return s;
+    if (sys->expr)
+        return fail(FF_E_UNSUPPORTED, "the adjoint needs the built-in right-hand sides' vector-Jacobian products");
     if (ff_status s = check_batch(sys, b, false)) return s;
     if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
     if (K < 1) return fail(FF_E_INVALID, "K must be >= 1");

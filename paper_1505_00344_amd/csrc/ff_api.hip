@@ -126,6 +126,7 @@ hipError_t launch_rk4(const ff_system_s* sys, const RK4Launch& L) {
         case FF_RHS_LORENZ: return launch_rk4_lorenz(L);
         case FF_RHS_WILSON_COWAN: return launch_rk4_wc(L);
         case FF_RHS_HH_RING: return launch_rk4_hh(sys->dim / 5, L);
+        case FF_RHS_EXPR: return launch_rk4_expr(sys, L);
     }
     return hipErrorInvalidValue;
 }
@@ -147,6 +148,7 @@ ff_status ff_system_create(int32_t rhs, int32_t dim, int32_t n_params, const dou
     *out = nullptr;
     const int want = expected_params(rhs, dim);
     if (want < 0) {
+        if (rhs == FF_RHS_EXPR) return fail(FF_E_INVALID, "expression systems are made by ff_system_create_expr");
         if (rhs < 0 || rhs > FF_RHS_HH_RING) return fail(FF_E_INVALID, "unknown right-hand side");
         if (rhs == FF_RHS_HH_RING && dim > 0 && dim % 5 == 0)
             return fail(FF_E_UNSUPPORTED, "Hodgkin-Huxley ring: this build has 1 or 3 neurons (dim 5 or 15)");
@@ -168,6 +170,7 @@ ff_status ff_system_create(int32_t rhs, int32_t dim, int32_t n_params, const dou
 
 ff_status ff_system_destroy(ff_system_t sys) {
     g_error.clear();
+    if (sys) expr_destroy(sys->expr);
     delete sys;
     return FF_OK;
 }
@@ -208,6 +211,9 @@ ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int
     if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
     if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    if (sys->expr) {
+        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+    }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
     for (int64_t done = 0; done < nsteps;) {
@@ -276,6 +282,9 @@ extern "C" ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, doub
     ResetArgs r;
     if (ff_status s = fill_reset(sys, b, reset, &r)) return s;
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    if (sys->expr) {
+        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+    }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
     L.reset = &r;
@@ -298,6 +307,9 @@ extern "C" ff_status ff_integrate_record(ff_system_t sys, const ff_batch* b, dou
         if (ff_status s = fill_reset(sys, b, reset, &r)) return s;
     }
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
+    if (sys->expr) {
+        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+    }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
     RecordArgs rc;

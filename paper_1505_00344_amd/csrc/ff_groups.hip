@@ -205,6 +205,8 @@ ff_status prepare(const ff_group* groups, int32_t n_groups, const ff_tuning& t, 
     for (int i = 0; i < n_groups; ++i) {
         const ff_group& g = groups[i];
         if (ff_status s = check_system(g.sys)) return s;
+        if (g.sys->expr)
+            return fail(FF_E_UNSUPPORTED, "the ragged-batch kernel holds the built-in right-hand sides only");
         if (ff_status s = check_batch(g.sys, &g.b, true)) return s;
         if (!std::isfinite(g.dt_signed)) return fail(FF_E_INVALID, "group dt_signed is not finite");
         if (g.b.n > 0x7fffffffLL) return fail(FF_E_UNSUPPORTED, "group larger than 2^31 - 1 particles");

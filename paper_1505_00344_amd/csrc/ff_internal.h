@@ -7,18 +7,11 @@
 #include <string>
 
 #include "../../include/fireflies.h"
+#include "ff_kernel.h"
 
 namespace ff {
 
-constexpr int kMaxParams = 16;
-constexpr int kMaxPP = FF_MAX_PP;
-constexpr int kMaxDim = 15;
-struct ResetArgs;
-struct RecordArgs;
-
-struct ParamBlock {
-    double v[kMaxParams];
-};
+static_assert(kMaxPP == FF_MAX_PP, "kernel and ABI disagree on per-particle parameters");
 
 // Everything one fused-RK4 launch needs (kernel arguments are built from it).
 struct RK4Launch {
@@ -74,6 +67,10 @@ hipError_t launch_adj_lorenz(const AdjLaunch& A);
 hipError_t launch_adj_wc(const AdjLaunch& A);
 hipError_t launch_adj_hh(int neurons, const AdjLaunch& A);
 
+// Right-hand sides compiled at run time from expressions (ff_expr.hip).
+struct ExprProgram;
+constexpr int kExprKernels = 8;  // {step, reset, record, record+reset} x {1, 2} particles per thread
+
 // Thread-local last-error text.
 void set_error(const std::string& msg);
 ff_status fail(ff_status code, const std::string& msg);
@@ -87,6 +84,7 @@ struct ff_system_s {
     int32_t dim;
     int32_t n_params;
     double params[ff::kMaxParams];
+    ff::ExprProgram* expr = nullptr;  // FF_RHS_EXPR only
 };
 
 namespace ff {
@@ -102,6 +100,11 @@ RK4Launch make_launch(const ff_system_s* sys, const ff_batch* b, double dt, cons
                       hipStream_t stream);
 // Launch the fused RK4 kernel of the system for L.steps steps.
 hipError_t launch_rk4(const ff_system_s* sys, const RK4Launch& L);
+// Expression systems: compile and load the kernels of `prec` for the current
+// device unless that was done before (thread-safe).
+ff_status expr_prepare(const ff_system_s* sys, int prec);
+hipError_t launch_rk4_expr(const ff_system_s* sys, const RK4Launch& L);
+void expr_destroy(ExprProgram* p);
 // Default particles per thread / block for a system and precision.
 ff_tuning default_tuning(const ff_system_s* sys, int prec, int64_t nsteps);
 

@@ -20,48 +20,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-namespace ff {
+#include "ff_math.h"
 
-// ---------------------------------------------------------------- math
-template <typename R> struct M;
-template <> struct M<double> {
-    static constexpr bool kFast = false;
-    static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-    // exp(x * c) for a compile-time constant c: the product is rounded, then exp
-    static __device__ __forceinline__ double expc(double x, double c) { return exp(x * c); }
-    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
-    static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
-};
-// Single precision.  By default (FF_FAST_F32 = 1) the exponential is the
-// hardware 2^x (v_exp_f32) with log2(e) folded into the argument's scale, and
-// reciprocals/divisions use v_rcp_f32 (each about 1 ulp); expm1 stays the
-// library function because psi(u) near u = 0 needs it.  FF_FAST_F32 = 0 uses
-// the library expf and correctly rounded division instead.  Double precision
-// always uses the library exp/expm1 and correctly rounded division.
-#ifndef FF_FAST_F32
-#define FF_FAST_F32 1
-#endif
-constexpr double kLog2e = 1.4426950408889634074;
-template <> struct M<float> {
-    static constexpr bool kFast = FF_FAST_F32 != 0;
-    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-#if FF_FAST_F32
-    static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * (float)kLog2e); }
-    static __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
-    static __device__ __forceinline__ float expc(float x, double c) { return __builtin_amdgcn_exp2f(x * (float)(c * kLog2e)); }
-    static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-#else
-    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
-    static __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
-    static __device__ __forceinline__ float expc(float x, double c) { return expf(x * (float)c); }
-    static __device__ __forceinline__ float rcp_(float x) { return 1.0f / x; }
-    static __device__ __forceinline__ float div_(float a, float b) { return a / b; }
-#endif
-    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
-};
+namespace ff {
 
 // ---------------------------------------------------------------- linear
 // x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.

@@ -4,9 +4,16 @@
 // multiplications (multipliers 0xD2511F53 and 0xCD9E8D57) and xors, the key
 // advancing by the Weyl increments 0x9E3779B9 and 0xBB67AE85 between rounds.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#else
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace ff {
 

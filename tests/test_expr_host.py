@@ -1,0 +1,137 @@
+"""CPU checks of the library's expression systems (ff_system_create_expr,
+ff_system_source, ff_system_compile with an explicit architecture): parsing
+and its errors, the generated kernel source, and a gfx950 compilation that
+needs no device.  The kernels themselves run in the GPU tests."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from expr_cases import BAD, CONSTANTS, LORENZ_EXPR, QUAD_EXPRS, WC_EXPR
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1505_00344_amd import api
+    api._ffi.lib()
+    return api
+
+
+def test_info_and_params(A):
+    s = A.System.from_exprs(LORENZ_EXPR, [10.0, 28.0, 8 / 3])
+    rhs, dim, npar = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    A.call("ff_system_info", s.handle, ctypes.byref(rhs), ctypes.byref(dim), ctypes.byref(npar))
+    assert (rhs.value, dim.value, npar.value) == (A._ffi.FF_RHS_EXPR, 3, 3)
+    s.set_params([1.0, 2.0, 3.0])
+    assert s.get_params() == [1.0, 2.0, 3.0]
+
+
+@pytest.mark.parametrize("text", BAD)
+def test_library_rejects_what_the_oracle_rejects(A, ora, text):
+    with pytest.raises(ValueError):
+        ora.expr_rk4([text, "x0", "x1"], [], np.zeros((3, 1)), 0.1, 1)
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_INVALID.*column"):
+        A.System.from_exprs([text, "x0", "x1"])
+
+
+@pytest.mark.parametrize("text", [e for e, _ in CONSTANTS] + QUAD_EXPRS + LORENZ_EXPR)
+def test_library_accepts_what_the_oracle_accepts(A, ora, text):
+    ora.expr_rk4([text, "x0", "x1"], [1.0, 2.0, 3.0], np.zeros((3, 1)), 0.1, 1)
+    A.System.from_exprs([text, "x0", "x1"], [1.0, 2.0, 3.0])
+
+
+def test_error_names_variable_and_column(A):
+    with pytest.raises(A._ffi.FirefliesError, match=r"x1, column 6: unknown name 'foo'"):
+        A.System.from_exprs(["x0", "1 + (foo(x0))"])
+
+
+@pytest.mark.parametrize("dim,npar,exprs,params", [
+    (0, 0, [], []), (16, 0, ["1"] * 16, []), (1, 17, ["1"], [0.0] * 17)])
+def test_size_limits(A, dim, npar, exprs, params):
+    arr = (ctypes.c_char_p * max(len(exprs), 1))(*[e.encode() for e in exprs])
+    p = (ctypes.c_double * max(len(params), 1))(*params)
+    h = ctypes.c_void_p()
+    assert A._ffi.lib().ff_system_create_expr(dim, arr, npar, p, ctypes.byref(h)) == A._ffi.FF_E_INVALID
+
+
+def test_nesting_and_size_limits(A):
+    with pytest.raises(A._ffi.FirefliesError, match="nested deeper"):
+        A.System.from_exprs(["(" * 300 + "x0" + ")" * 300])
+    A.System.from_exprs(["(" * 200 + "x0" + ")" * 200])
+    big = " + ".join(f"{k}*x0" for k in range(3000))  # 6000 distinct operations
+    with pytest.raises(A._ffi.FirefliesError, match="too large"):
+        A.System.from_exprs([big])
+
+
+def test_builtin_create_refuses_expr_kind(A):
+    h = ctypes.c_void_p()
+    p = (ctypes.c_double * 1)(0.0)
+    assert A._ffi.lib().ff_system_create(A._ffi.FF_RHS_EXPR, 1, 0, p, ctypes.byref(h)) == A._ffi.FF_E_INVALID
+
+
+def test_source_shares_subtrees_and_hoists_parameter_terms(A):
+    s = A.System.from_exprs(["exp(p0*p1) * x0 + exp(p0*p1)", "sin(x0)*sin(x0) - p1"], [0.5, 2.0])
+    src = s.source("fp64")
+    # exp(p0*p1) is state-free: computed once per particle in derive()
+    derive, f = src.split("void f(")
+    assert derive.count("exp(") == 1 and "exp(" not in f
+    # sin(x0) appears twice in the text and once in the code
+    assert f.count("sin(") == 1
+    assert "sinf(" in s.source("fp32") and "sinf(" in s.source("fp32_kahan")
+    assert "ff::k_rk4" not in src  # instances are requested by name at compile time
+
+
+def test_literals_are_exact(A):
+    s = A.System.from_exprs(["0.1 * x0 + 1e999 - 5e-324"])
+    src = s.source("fp64")
+    assert "0x1.999999999999ap-4" in src and "__builtin_huge_val()" in src
+    assert "0x0.0000000000001p-1022" in src or "0x1p-1074" in src
+    assert "((float)(0x1.999999999999ap-4))" in s.source("fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_compiles_for_gfx950_without_a_device(A, prec):
+    s = A.System.from_exprs(WC_EXPR, [1.0] * 10)
+    s.compile(prec, arch="gfx950")
+    q = A.System.from_exprs(["1"] + QUAD_EXPRS)
+    q.compile(prec, arch="gfx950")
+
+
+def test_adjoint_and_groups_refuse_expression_systems(A):
+    from paper_1505_00344_amd import _ffi
+    L = _ffi.lib()
+    s = A.System.from_exprs(LORENZ_EXPR, [10.0, 28.0, 8 / 3])
+    b = _ffi.Batch()
+    b.prec, b.state, b.n, b.ld = _ffi.FF_FP64, 4096, 10, 10
+    sz = ctypes.c_size_t()
+    assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz)) == _ffi.FF_E_UNSUPPORTED
+    assert L.ff_integrate_checkpointed(s.handle, ctypes.byref(b), 0.01, 100, 10, None, 0, None) == \
+        _ffi.FF_E_UNSUPPORTED
+    g = A.make_groups([(s, b, 0.01)])
+    assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == _ffi.FF_E_UNSUPPORTED
+
+
+def test_noop_calls_compile_nothing(A):
+    # n == 0, nsteps == 0 or dt == 0 return before any compilation or device use
+    from paper_1505_00344_amd import _ffi
+    L = _ffi.lib()
+    s = A.System.from_exprs(LORENZ_EXPR, [10.0, 28.0, 8 / 3])
+    b = _ffi.Batch()
+    b.prec, b.state, b.n, b.ld = _ffi.FF_FP64, 4096, 10, 10
+    assert L.ff_integrate(s.handle, ctypes.byref(b), 0.0, 100, None, None) == 0
+    assert L.ff_integrate(s.handle, ctypes.byref(b), 0.01, 0, None, None) == 0
+
+
+def test_make_reset_checks_tensor_sizes(A):
+    import torch
+    age = torch.zeros(10, dtype=torch.int32)
+    nres = torch.zeros(10, dtype=torch.int32)
+    box = [(-1.0, 1.0)] * 3
+    r = A.make_reset(box, box, age, nres, 10)
+    assert r.age == age.data_ptr()
+    r = A.make_reset(box, box, age, nres, 4, offset=6)
+    assert r.age == age.data_ptr() + 24
+    with pytest.raises(ValueError):
+        A.make_reset(box, box, age, nres, 5, offset=6)
+    with pytest.raises(ValueError):
+        A.make_reset(box, box, age.to(torch.int64), nres, 10)

@@ -1,0 +1,200 @@
+"""GPU parity of expression systems (Appendix A: a State Variable's
+right-hand side is an expression; Appendix A.1: it is filled into the step
+kernel, compiled at run time) against the oracle's expression evaluator.
+
+Expressions made of +, -, *, / and fma are correctly rounded operations on
+both sides: identical bits.  Expressions with exp, sin, ... compare two math
+libraries (each within a few ulp): the tolerances of the built-in systems
+that call exp apply."""
+import numpy as np
+import pytest
+
+import tolerances as tol
+from expr_cases import LORENZ_EXPR, QUAD_EXPRS, WC_EXPR
+from helpers import api, f32_inputs, finite_cols, mixed_error, quantiles, record, to_dev, to_host
+from paper_1505_00344_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# a rational system (van der Pol with a saturating drive): arithmetic only
+RATIONAL = ["x1", "p0*(1 - x0*x0)*x1 - x0 + p1*x2/(1 + x2*x2)", "-x2/p2 + x0*x1/(3 + x0*x0)"]
+
+
+@pytest.fixture(scope="module")
+def A():
+    return api()
+
+
+def run(A, sysobj, x, dt, nsteps, dtype, pp=None, pp_slot=(), kahan=False, tuning=None, n=None, offset=0):
+    st = to_dev(x, dtype)
+    ppt = None if pp is None else to_dev(pp, dtype)
+    comp = torch.zeros_like(st) if kahan else None
+    A.integrate(sysobj, st, dt, nsteps, pparams=ppt, pp_slot=pp_slot, comp=comp, tuning=tuning, n=n,
+                offset=offset)
+    torch.cuda.synchronize()
+    return to_host(st), (None if comp is None else to_host(comp))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_kahan"])
+@pytest.mark.parametrize("tuning", [None, (37, 2, 128), (200, 1, 64)])
+def test_lorenz_expressions_bitwise(A, ora, prec, tuning):
+    w = I.lorenz_4096()
+    e = I.generate(w)
+    nf = e.counts[0]
+    x = e.state[:, :nf]
+    rng = np.random.default_rng(7)
+    pp = rng.uniform(24.0, 32.0, (1, nf))
+    s_expr = A.System.from_exprs(LORENZ_EXPR, w.params)
+    s_builtin = A.System("lorenz", 3, w.params)
+    if prec == "fp64":
+        got, _ = run(A, s_expr, x, 0.005, 400, torch.float64, pp=pp, pp_slot=[1], tuning=tuning)
+        ref = ora.expr_rk4(LORENZ_EXPR, w.params, x, 0.005, 400, pp_slot=[1], pparams=pp)
+        same, _ = run(A, s_builtin, x, 0.005, 400, torch.float64, pp=pp, pp_slot=[1], tuning=tuning)
+        assert np.array_equal(got, ref) and np.array_equal(got, same)
+    else:
+        kahan = prec == "fp32_kahan"
+        x32, pp32 = x.astype(np.float32), pp.astype(np.float32)
+        got, c = run(A, s_expr, x32, 0.005, 400, torch.float32, pp=pp32, pp_slot=[1], kahan=kahan, tuning=tuning)
+        ref, cref = ora.expr_rk4_f32(LORENZ_EXPR, w.params, x32, 0.005, 400, pp_slot=[1], pparams=pp32, kahan=kahan)
+        same, csame = run(A, s_builtin, x32, 0.005, 400, torch.float32, pp=pp32, pp_slot=[1], kahan=kahan,
+                          tuning=tuning)
+        assert np.array_equal(got, ref) and np.array_equal(got, same)
+        if kahan:
+            assert np.array_equal(c, cref) and np.array_equal(c, csame)
+
+
+@pytest.mark.parametrize("n", [1, 255, 256 * 3 + 17])
+def test_rational_system_bitwise(A, ora, n):
+    rng = np.random.default_rng(n)
+    x = rng.uniform(-2, 2, (3, n))
+    params = [1.5, 0.7, 2.0]
+    s = A.System.from_exprs(RATIONAL, params)
+    got, _ = run(A, s, x, 0.01, 300, torch.float64)
+    assert np.array_equal(got, ora.expr_rk4(RATIONAL, params, x, 0.01, 300))
+    for kahan in (False, True):
+        x32 = x.astype(np.float32)
+        got, c = run(A, s, x32, -0.01, 300, torch.float32, kahan=kahan)
+        ref, cref = ora.expr_rk4_f32(RATIONAL, params, x32, -0.01, 300, kahan=kahan)
+        assert np.array_equal(finite_cols(got), finite_cols(ref))
+        fin = finite_cols(ref)
+        assert np.array_equal(got[:, fin], ref[:, fin])
+        if kahan:
+            assert np.array_equal(c[:, fin], cref[:, fin])
+
+
+def test_slice_with_offset_and_ld(A, ora):
+    # particles 100..899 of a (3, 1000) array; the rest stay untouched
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-2, 2, (3, 1000))
+    params = [1.5, 0.7, 2.0]
+    s = A.System.from_exprs(RATIONAL, params)
+    got, _ = run(A, s, x, 0.01, 50, torch.float64, n=800, offset=100)
+    assert np.array_equal(got[:, :100], x[:, :100]) and np.array_equal(got[:, 900:], x[:, 900:])
+    assert np.array_equal(got[:, 100:900], ora.expr_rk4(RATIONAL, params, x[:, 100:900], 0.01, 50))
+
+
+def test_wilson_cowan_expressions_fp64(A, ora):
+    w = I.wilson_cowan_4m(n=8192 + 77)
+    e = I.generate(w)
+    nf = e.counts[0]
+    s = A.System.from_exprs(WC_EXPR, w.params)
+    x, pp = e.state[:, :nf], e.pparams[:, :nf]
+    got, _ = run(A, s, x, e.dts[0], w.nsteps, torch.float64, pp=pp, pp_slot=w.pp_slot)
+    ref = ora.expr_rk4(WC_EXPR, w.params, x, e.dts[0], w.nsteps, pp_slot=w.pp_slot, pparams=pp)
+    err = mixed_error(got, ref)
+    record("expr_wc_fp64_forward", err=quantiles(err))
+    assert err.max() <= tol.FP64_REL, quantiles(err)
+
+
+def test_wilson_cowan_expressions_fp32_vs_fp64(A, ora):
+    w = I.wilson_cowan_4m(n=20000)
+    e = I.generate(w)
+    nf = e.counts[0]
+    x, pp = f32_inputs(e.state[:, :nf]), f32_inputs(e.pparams[:, :nf])
+    h = float(np.float32(0.01))
+    ref = ora.expr_rk4(WC_EXPR, w.params, x, h, w.nsteps, pp_slot=w.pp_slot, pparams=pp)
+    s = A.System.from_exprs(WC_EXPR, w.params)
+    errs = {}
+    for kahan in (False, True):
+        got, _ = run(A, s, x.astype(np.float32), h, w.nsteps, torch.float32, pp=pp.astype(np.float32),
+                     pp_slot=w.pp_slot, kahan=kahan)
+        errs[kahan] = mixed_error(got, ref)
+    record("expr_wc_fp32_vs_fp64", plain=quantiles(errs[False]), kahan=quantiles(errs[True]))
+    assert np.quantile(errs[False], 0.99) <= tol.FP32_WC_P99, quantiles(errs[False])
+    assert np.median(errs[True]) <= tol.KAHAN_WC_MEDIAN, quantiles(errs[True])
+    assert np.quantile(errs[True], 0.99) <= tol.KAHAN_WC_P99, quantiles(errs[True])
+
+
+def test_every_function_fp64_and_fp32(A, ora):
+    # x0' = 1 is time and x_k' = g_k(x0): 15 components, each function once;
+    # particles start at different times in [0, 0.5]
+    exprs = ["1"] + QUAD_EXPRS
+    n = 1000
+    x = np.zeros((15, n))
+    x[0] = np.linspace(0.0, 0.5, n)
+    s = A.System.from_exprs(exprs)
+    got, _ = run(A, s, x, 0.005, 100, torch.float64)
+    ref = ora.expr_rk4(exprs, [], x, 0.005, 100)
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    record("expr_functions_fp64", err=quantiles(err.ravel()))
+    assert err.max() <= tol.FP64_REL
+    x32 = x.astype(np.float32)
+    got, _ = run(A, s, x32, 0.005, 100, torch.float32)
+    ref32, _ = ora.expr_rk4_f32(exprs, [], x32, 0.005, 100)
+    err = np.abs(got - ref32) / np.maximum(np.abs(ref32), 1.0)
+    record("expr_functions_fp32", err=quantiles(err.ravel()))
+    # 100 steps, each adding h/6-weighted values that differ by a few float ulp
+    assert err.max() <= 1e-5
+
+
+def test_reset_and_record_with_expressions(A, ora):
+    w = I.lorenz_4096()
+    e = I.generate(w)
+    nf = e.counts[0]
+    x0 = e.state[:, nf:]
+    n = x0.shape[1]
+    bounds = [(-40.0, 40.0), (-60.0, 60.0), (-10.0, 80.0)]
+    s = A.System.from_exprs(LORENZ_EXPR, w.params)
+    st = to_dev(x0, torch.float64)
+    age = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    nres = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    out = A.integrate_record(s, st, -0.005, 300, 50, 1,
+                             reset=dict(bounds=bounds, box=I.LORENZ_BOX, age=age, n_resets=nres, seed=5,
+                                        max_age=120))
+    torch.cuda.synchronize()
+    rec = to_host(out)
+    ref, a, r = x0.copy(), None, None
+    for k in range(6):
+        ref, _, a, r = ora.rk4_reset(ora.LORENZ, w.params, ref, -0.005, 50, bounds, I.LORENZ_BOX, max_age=120,
+                                     seed=5, age=a, n_resets=r)
+        assert np.array_equal(rec[k], ref), k
+    assert np.array_equal(to_host(age), a) and np.array_equal(to_host(nres).view(np.uint32), r)
+    # reset alone
+    st = to_dev(x0, torch.float64)
+    age.zero_()
+    nres.zero_()
+    A.integrate_reset(s, st, -0.005, 300, bounds=bounds, box=I.LORENZ_BOX, age=age, n_resets=nres, seed=5,
+                      max_age=120)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(st), ref)
+
+
+def test_explicit_compile_then_many_systems(A, ora):
+    # compile ahead of use; several live systems with their own modules
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (1, 300))
+    systems = []
+    for k in range(4):
+        s = A.System.from_exprs([f"-{k + 1}*x0 + p0"], [0.25 * k])
+        s.compile("fp64")
+        systems.append(s)
+    for k, s in enumerate(systems):
+        got, _ = run(A, s, x, 0.01, 100, torch.float64)
+        assert np.array_equal(got, ora.expr_rk4([f"-{k + 1}*x0 + p0"], [0.25 * k], x, 0.01, 100))
+    # new parameter values need no recompilation
+    systems[0].set_params([2.0])
+    got, _ = run(A, systems[0], x, 0.01, 100, torch.float64)
+    assert np.array_equal(got, ora.expr_rk4(["-1*x0 + p0"], [2.0], x, 0.01, 100))
+    del systems

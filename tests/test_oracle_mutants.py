@@ -1,7 +1,8 @@
 """The pins must catch plausible mistakes in the oracle.
 
 Each case plants one mistake (a wrong weight, sign, index or operand, a
-dropped term) in a copy of oracle/ffo.cpp, builds it on the CPU, points the
+dropped term) in a copy of oracle/ffo.cpp (or oracle/ffo_expr.cpp for the
+expression evaluator), builds it on the CPU, points the
 oracle wrapper at it (FFO_LIB) and runs the pin tests in a subprocess: at
 least one pin must fail.  The unmodified source must pass the same run.
 """
@@ -13,7 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "ffo.cpp")
-PINS = ["tests/test_oracle_tableau.py", "tests/test_oracle_linear.py", "tests/test_oracle_lorenz.py",
+SRC_EXPR = os.path.join(ROOT, "oracle", "ffo_expr.cpp")
+PINS = ["tests/test_oracle_expr.py", "tests/test_oracle_tableau.py", "tests/test_oracle_linear.py", "tests/test_oracle_lorenz.py",
         "tests/test_oracle_wilson_cowan.py", "tests/test_oracle_hh.py", "tests/test_oracle_adjoint.py",
         "tests/test_oracle_histogram.py", "tests/test_oracle_reset.py"]
 
@@ -47,13 +49,34 @@ MUTANTS = {
                        "if (escaped(dim, x, bound_lo, bound_hi) || (max_age >= 0 && a >= max_age)) {\n                redraw(dim, box_lo, box_hi, seed, id_offset + (uint64_t)i, r, x);\n                a = 0;"),
 }
 
+# mistakes in the expression evaluator (oracle/ffo_expr.cpp)
+MUTANTS_EXPR = {
+    "expr_sub_operands": ("case Node::SUB: return eval(n->kids[0].get(), x, p) - eval(n->kids[1].get(), x, p);",
+                          "case Node::SUB: return eval(n->kids[1].get(), x, p) - eval(n->kids[0].get(), x, p);"),
+    "expr_sum_binds_product": ("            const char op = *s++;\n            auto b = term();",
+                               "            const char op = *s++;\n            auto b = unary();"),
+    "expr_right_assoc": ("            const char op = *s++;\n            auto b = term();",
+                         "            const char op = *s++;\n            auto b = expr();"),
+    "expr_function_table": ("case 5: return std::sin(a);", "case 5: return std::cos(a);"),
+    "expr_negation": ("case Node::NEG: return -eval(n->kids[0].get(), x, p);",
+                      "case Node::NEG: return eval(n->kids[0].get(), x, p);"),
+    "expr_stage4": ("for (int d = 0; d < dim; ++d) y[d] = std::fma(h, k3[d], x[d]);",
+                    "for (int d = 0; d < dim; ++d) y[d] = std::fma(h2, k3[d], x[d]);"),
+    "expr_pp_slot": ("for (int q = 0; q < n_pp; ++q) p[pp_slot[q]] = pparams[q * ld + i];",
+                     "for (int q = 0; q < n_pp; ++q) p[q] = pparams[q * ld + i];"),
+    "expr_kahan_sign": ("c[d] = (t - x[d]) - yk;", "c[d] = (t - x[d]) + yk;"),
+}
 
-def build_variant(tmp_path, name, text):
+
+def build_variant(tmp_path, name, text, text_expr=None):
     src = tmp_path / f"{name}.cpp"
     src.write_text(text)
+    src_expr = tmp_path / f"{name}_expr.cpp"
+    src_expr.write_text(text_expr if text_expr is not None else open(SRC_EXPR).read())
     lib = tmp_path / f"{name}.so"
     subprocess.run(["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                    "-shared", "-I", os.path.join(ROOT, "oracle"), str(src), "-o", str(lib)], check=True)
+                    "-shared", "-I", os.path.join(ROOT, "oracle"), str(src), str(src_expr), "-o", str(lib)],
+                   check=True)
     return lib
 
 
@@ -76,5 +99,15 @@ def test_pins_catch_mutant(tmp_path, name):
     text = open(SRC).read()
     assert text.count(before) == 1, f"mutation site of {name} not found exactly once"
     lib = build_variant(tmp_path, name, text.replace(before, after))
+    rc, out = run_pins(lib)
+    assert rc != 0, f"no pin failed for mutant {name}:\n{out}"
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_EXPR))
+def test_pins_catch_expression_mutant(tmp_path, name):
+    before, after = MUTANTS_EXPR[name]
+    text = open(SRC_EXPR).read()
+    assert text.count(before) == 1, f"mutation site of {name} not found exactly once"
+    lib = build_variant(tmp_path, name, open(SRC).read(), text.replace(before, after))
     rc, out = run_pins(lib)
     assert rc != 0, f"no pin failed for mutant {name}:\n{out}"
