@@ -47,9 +47,10 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
 # Sources that define the dominant kernel; the HBM traffic measured with
 # rocprofv3 counters is reported only while their hash matches the one
 # recorded next to the counters in profiles/.
-KERNEL_SOURCES = ["paper_1505_00344_amd/csrc/ff_rhs.h", "paper_1505_00344_amd/csrc/ff_rk4.h",
-                  "paper_1505_00344_amd/csrc/ff_internal.h", "paper_1505_00344_amd/csrc/k_rk4_wc.hip",
-                  "paper_1505_00344_amd/build.py"]
+KERNEL_SOURCES = ["paper_1505_00344_amd/csrc/ff_rhs.h", "paper_1505_00344_amd/csrc/ff_math.h",
+                  "paper_1505_00344_amd/csrc/ff_kernel.h", "paper_1505_00344_amd/csrc/ff_rng.h",
+                  "paper_1505_00344_amd/csrc/ff_rk4.h", "paper_1505_00344_amd/csrc/ff_internal.h",
+                  "paper_1505_00344_amd/csrc/k_rk4_wc.hip", "paper_1505_00344_amd/build.py"]
 COUNTERS_FILE = "profiles/wc4m_fp32kahan_hbm_counters.md"
 
 
@@ -82,8 +83,8 @@ METRIC = "particle-RK4-steps/s (FP32-comp vs FP64) + % VALU peak; adjoint steps/
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--particles", type=int, default=4 * 1024 * 1024)
     ap.add_argument("--rk4-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -369,7 +370,102 @@ def extended(A, I, torch, np):
                 "particle_steps_per_s_batched": ntot * nsteps / (batched * 1e-3),
                 "frame_ms_p50": float(np.percentile(frames, 50)), "frame_ms_p99": float(np.percentile(frames, 99))}
 
-    for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed)):
+    def next_rows():
+        """Reset rule, trajectory recording, render technique and expression
+        right-hand sides on the paper's large ensembles."""
+        r = {}
+        w = I.lorenz_8m()
+        e = I.generate(w)
+        n, steps = w.n, w.nsteps
+        st0 = torch.as_tensor(e.state, dtype=torch.float32, device=dev)
+        pp = torch.as_tensor(e.pparams, dtype=torch.float32, device=dev).contiguous()
+        builtin = A.System("lorenz", 3, w.params)
+
+        def rate(fn, reps=3):
+            fn()
+            ms = _time_stream(torch, fn, reps=reps)
+            return {"ms": ms, "particle_steps_per_s": n * steps / (ms * 1e-3)}
+
+        st, comp = st0.clone(), torch.zeros_like(st0)
+        plain = rate(lambda: A.integrate(builtin, st, 0.005, steps, pparams=pp, pp_slot=w.pp_slot, comp=comp))
+        r["lorenz_8m_fp32_kahan_plain"] = plain
+        # N1: backward in time with the reset rule (escaping particles redrawn in the box)
+        bounds = [(-60.0, 60.0), (-80.0, 80.0), (-30.0, 100.0)]
+        age = torch.zeros(n, dtype=torch.int32, device=dev)
+        nres = torch.zeros(n, dtype=torch.int32, device=dev)
+        st, comp = st0.clone(), torch.zeros_like(st0)
+        res = rate(lambda: A.integrate_reset(builtin, st, -0.005, steps, bounds=bounds, box=I.LORENZ_BOX, age=age,
+                                             n_resets=nres, seed=1, max_age=400, pparams=pp, pp_slot=w.pp_slot,
+                                             comp=comp))
+        res["resets_per_particle_step"] = float(nres.double().sum().item()) / (4 * n * steps)
+        r["reset_lorenz_8m_backward_fp32_kahan"] = res
+        # N4: record every 10th step of every 16th particle
+        st, comp = st0.clone(), torch.zeros_like(st0)
+        out = torch.empty((steps // 10, 3, (n + 15) // 16), dtype=torch.float32, device=dev)
+        rec = rate(lambda: A.integrate_record(builtin, st, 0.005, steps, 10, 16, out=out, pparams=pp,
+                                              pp_slot=w.pp_slot, comp=comp))
+        rec["record_bytes"] = out.numel() * 4
+        rec["slowdown_vs_plain"] = rec["ms"] / plain["ms"]
+        r["record_lorenz_8m_every10_stride16"] = rec
+        del out
+        # N3: 8M particles drawn into a 1920 x 1080 frame, perspective camera
+        f = 1.0 / np.tan(np.radians(60.0) / 2)
+        aspect, near, far = 1920 / 1080, 1.0, 400.0
+        proj = np.array([[f / aspect, 0, 0, 0], [0, f, 0, 0],
+                         [0, 0, (far + near) / (near - far), 2 * far * near / (near - far)], [0, 0, -1, 0]])
+        view = np.eye(4)
+        view[:3, 3] = [0.0, -25.0, -120.0]
+        view[:3, :3] = [[1, 0, 0], [0, 0, 1], [0, -1, 0]]  # look along +y with z up
+        mvp = proj @ view
+        img = torch.empty((1080, 1920, 3), dtype=torch.int32, device=dev)
+        culled = torch.empty(1, dtype=torch.int64, device=dev)
+        for radius in (0, 2):
+            def draw():
+                A.render_image(builtin, st, (0, 1, 2), mvp, 1920, 1080, base=(0.2, 0.5, 1.0),
+                               grad=[[0.01, 0, 0], [0, 0, 0], [0, 0, 0.01]], weight=0.05, radius=radius, img=img,
+                               n_culled=culled)
+            draw()
+            ms = _time_stream(torch, draw, reps=5)
+            r[f"render_8m_1080p_radius{radius}"] = {"ms": ms, "particles_per_s": n / (ms * 1e-3),
+                                                    "culled": int(culled.item())}
+        del img
+        # N2: the same systems given as expressions (compiled at run time)
+        lorenz_expr = A.System.from_exprs(["p0*(x1-x0)", "fma(x0, p1-x2, -x1)", "fma(x0, x1, -(p2*x2))"], w.params)
+        t0 = time.perf_counter()
+        lorenz_expr.compile("fp32_kahan")
+        compile_s = time.perf_counter() - t0
+        st, comp = st0.clone(), torch.zeros_like(st0)
+        ex = rate(lambda: A.integrate(lorenz_expr, st, 0.005, steps, pparams=pp, pp_slot=w.pp_slot, comp=comp))
+        ex["vs_builtin"] = ex["particle_steps_per_s"] / plain["particle_steps_per_s"]
+        ex["compile_s"] = compile_s
+        r["expr_lorenz_8m_fp32_kahan"] = ex
+        del st, comp, st0, pp, age, nres
+        wc = I.wilson_cowan_4m()
+        ew = I.generate(wc)
+        nf = ew.counts[0]
+        wc_expr = A.System.from_exprs(["1/(1+exp(-(p4*(fma(p0, x0, fma(-p1, x1, p8)) - p5)))) - x0",
+                                       "1/(1+exp(-(p6*(fma(p2, x0, fma(-p3, x1, p9)) - p7)))) - x1"], wc.params)
+        wc_builtin = A.System("wilson_cowan", 2, wc.params)
+        for prec in ("fp32_kahan", "fp64"):
+            dt_ = torch.float64 if prec == "fp64" else torch.float32
+            x = torch.as_tensor(ew.state[:, :nf], dtype=dt_, device=dev).contiguous()
+            p_ = torch.as_tensor(ew.pparams[:, :nf], dtype=dt_, device=dev).contiguous()
+            out_ = {}
+            for name, sobj in (("builtin", wc_builtin), ("expr", wc_expr)):
+                xs = x.clone()
+                c_ = torch.zeros_like(xs) if prec == "fp32_kahan" else None
+
+                def go():
+                    A.integrate(sobj, xs, 0.01, wc.nsteps, pparams=p_, pp_slot=wc.pp_slot, comp=c_, prec=prec)
+                go()
+                ms = _time_stream(torch, go, reps=3)
+                out_[name] = {"ms": ms, "particle_steps_per_s": nf * wc.nsteps / (ms * 1e-3)}
+            out_["expr_vs_builtin"] = out_["expr"]["particle_steps_per_s"] / out_["builtin"]["particle_steps_per_s"]
+            r[f"expr_wc_2m_forward_{prec}"] = out_
+        return r
+
+    for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed),
+                     ("next_rows", next_rows)):
         try:
             res[name] = fn()
         except Exception as ex:  # report and continue with the next workload
@@ -409,9 +505,22 @@ def cpu_baseline(e, w, seconds):
     m_final = min(int(m * seconds / max(t, 1e-3)), min(e.counts))
     t = run(m_final)
     total = m_final * len(e.counts)
-    return {"value": total * w.nsteps / t, "unit": "particle-RK4-steps/s", "cores": threads, "kind": "oracle",
+    # one thread, for comparison with the paper's single-core column (smaller sample)
+    threads_all = threads
+    threads = 1
+    m1 = max(256, min(m_final, int(m_final * 1.5 / max(t * threads_all, 1e-3))))
+    t1 = run(m1)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": total * w.nsteps / t, "unit": "particle-RK4-steps/s", "cores": threads_all, "kind": "oracle",
             "sample": f"{total} of {w.n} particles (every k-th of each group), {w.nsteps} steps, FP64, "
-                      f"{t:.1f} s"}
+                      f"{t:.1f} s",
+            "value_1_thread": m1 * len(e.counts) * w.nsteps / t1,
+            "host": f"{model}; {os.cpu_count()} logical CPUs, {len(os.sched_getaffinity(0))} usable"}
 
 
 if __name__ == "__main__":

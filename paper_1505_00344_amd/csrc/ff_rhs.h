@@ -77,28 +77,50 @@ template <typename R> struct Lorenz {
 // E' = -E + S_E(c1 E - c2 I + P), I' = -I + S_I(c3 E - c4 I + Q),
 // S(u) = 1/(1 + exp(-a (u - th)));  p = [c1, c2, c3, c4, aE, thE, aI, thI, P, Q].
 template <typename R> struct WilsonCowan {
-    static constexpr int D = 2, NP = 10, NQ = 2;
-    // fast single precision: q = -a*log2(e) per population, so that
-    // S = 1/(1 + 2^((u - th) * q)) costs one sub, mul, exp2, add and rcp
+    // Fast single precision folds the gain into the sigmoid's argument: with
+    // g = -a*log2(e), (u - th)*g = fma(c1*g, E, fma(-c2*g, I, (P - th)*g)),
+    // three constants per population derived once per particle, so each
+    // S = 1/(1 + 2^z) costs two fma, exp2, add and rcp.  (The folded constants
+    // round the same number of times as the canonical order, with errors of
+    // the same size.)  Otherwise the canonical order below is kept.
+    static constexpr bool kFold = M<R>::kFast;
+    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1;
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
-        q[0] = -p[4] * R(kLog2e);
-        q[1] = -p[6] * R(kLog2e);
+        if constexpr (kFold) {
+            const R gE = -p[4] * R(kLog2e), gI = -p[6] * R(kLog2e);
+            q[0] = p[0] * gE;
+            q[1] = -p[1] * gE;
+            q[2] = (p[8] - p[5]) * gE;
+            q[3] = p[2] * gI;
+            q[4] = -p[3] * gI;
+            q[5] = (p[9] - p[7]) * gI;
+        } else {
+            q[0] = R(0);
+        }
     }
-    static __device__ __forceinline__ R sig(R a, R qa, R u, R th) {
-        if constexpr (M<R>::kFast) return M<R>::rcp_(R(1) + M<R>::exp2_((u - th) * qa));
-        else return M<R>::rcp_(R(1) + M<R>::exp_(-(a * (u - th))));
+    static __device__ __forceinline__ void sigmoids(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R& sE, R& sI) {
+        if constexpr (kFold) {
+            sE = M<R>::rcp_(R(1) + M<R>::exp2_(M<R>::fma_(q[0], x[0], M<R>::fma_(q[1], x[1], q[2]))));
+            sI = M<R>::rcp_(R(1) + M<R>::exp2_(M<R>::fma_(q[3], x[0], M<R>::fma_(q[4], x[1], q[5]))));
+        } else {
+            const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
+            const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
+            sE = M<R>::rcp_(R(1) + M<R>::exp_(-(p[4] * (uE - p[5]))));
+            sI = M<R>::rcp_(R(1) + M<R>::exp_(-(p[6] * (uI - p[7]))));
+        }
     }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R (&o)[D]) {
-        const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
-        const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-        o[0] = sig(p[4], q[0], uE, p[5]) - x[0];
-        o[1] = sig(p[6], q[1], uI, p[7]) - x[1];
+        R sE, sI;
+        sigmoids(p, q, x, sE, sI);
+        o[0] = sE - x[0];
+        o[1] = sI - x[1];
     }
     static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D],
                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
         const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-        const R sE = sig(p[4], q[0], uE, p[5]), sI = sig(p[6], q[1], uI, p[7]);
+        R sE, sI;
+        sigmoids(p, q, x, sE, sI);
         const R qE = sE * (R(1) - sE), qI = sI * (R(1) - sI);
         const R dE = p[4] * qE * a[0];   // dS_E/du_E * a_E
         const R dI = p[6] * qI * a[1];
