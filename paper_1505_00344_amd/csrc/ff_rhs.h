@@ -147,15 +147,29 @@ template <typename R> struct WilsonCowan {
 //   am = psi(-(V+40)/10), bm = 4 e^{-(V+65)/18}, ah = 0.07 e^{-(V+65)/20},
 //   bh = 1/(1 + e^{-(V+35)/10}), an = 0.1 psi(-(V+55)/10),
 //   bn = 0.125 e^{-(V+65)/80},  T = 1/(1 + e^{-sg (V - th)}),
-//   psi(u) = u / (e^u - 1) with psi(0) = 1 taken by a select.
+//   psi(u) = u / (e^u - 1) with psi(0) = 1 taken by a select (fast single
+//   precision: a Bernoulli series near 0 and the hardware exp2 elsewhere).
 template <typename R> struct HHRate {
     R am, bm, ah, bh, an, bn, tv;
 };
 
 template <typename R>
 __device__ __forceinline__ R hh_psi(R u) {
-    const R q = M<R>::div_(u, M<R>::expm1_(u));
-    return (u == R(0)) ? R(1) : q;
+    if constexpr (M<R>::kFast) {
+        // |u| < 1/2: the Bernoulli series of u/(e^u - 1),
+        // 1 - u/2 + u^2/12 - u^4/720 + u^6/30240 (the next term, u^8/1209600,
+        // is below 3.3e-9); otherwise u * rcp(2^(u log2 e) - 1) with the
+        // hardware exp2 and rcp (cancellation in e^u - 1 costs at most a
+        // factor 2.6 there).  Both are computed and one is selected.
+        const R w = u * u;
+        const R series = M<R>::fma_(w, M<R>::fma_(w, M<R>::fma_(w, R(1.0 / 30240.0), R(-1.0 / 720.0)), R(1.0 / 12.0)),
+                                    M<R>::fma_(R(-0.5), u, R(1)));
+        const R direct = u * M<R>::rcp_(M<R>::exp2_(u * R(kLog2e)) - R(1));
+        return __builtin_fabsf(u) < R(0.5) ? series : direct;
+    } else {
+        const R q = M<R>::div_(u, M<R>::expm1_(u));
+        return (u == R(0)) ? R(1) : q;
+    }
 }
 
 template <typename R>
