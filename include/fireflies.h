@@ -157,7 +157,8 @@ ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n
  * Nothing is compiled here: ff_integrate, ff_integrate_reset and
  * ff_integrate_record compile the kernels of the batch's precision for the
  * current device on first use (hipRTC; about a second) and keep them with the
- * handle.  The adjoint and the ragged-batch calls (ff_integrate_groups,
+ * handle (ff_system_destroy waits for the device before unloading them).
+ * The adjoint and the ragged-batch calls (ff_integrate_groups,
  * ff_autotune) hold compiled-in right-hand sides only and return
  * FF_E_UNSUPPORTED for such a system. */
 ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n_params,

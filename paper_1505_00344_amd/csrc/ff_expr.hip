@@ -282,13 +282,18 @@ struct ExprProgram {
     };
     std::map<std::pair<int, int>, Module> modules;  // (device, prec)
 
+    // Unloading a code object while its kernels are queued or running is
+    // undefined, so each device is drained first (destroying a system is rare).
     ~ExprProgram() {
         if (modules.empty()) return;
         int cur = 0;
         const bool have = hipGetDevice(&cur) == hipSuccess;
         for (auto& kv : modules) {
             if (!kv.second.mod) continue;
-            if (hipSetDevice(kv.first.first) == hipSuccess) (void)hipModuleUnload(kv.second.mod);
+            if (hipSetDevice(kv.first.first) == hipSuccess) {
+                (void)hipDeviceSynchronize();
+                (void)hipModuleUnload(kv.second.mod);
+            }
         }
         if (have) (void)hipSetDevice(cur);
     }
@@ -398,7 +403,12 @@ ff_status compile(const ExprProgram& P, int prec, const std::string& arch, std::
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "ff_user_rhs.hip", 3, kHeaders, kHeaderNames) != HIPRTC_SUCCESS)
         return fail(FF_E_DEVICE, "hiprtcCreateProgram failed");
-    for (const std::string& n : names) hiprtcAddNameExpression(prog, n.c_str());
+    for (const std::string& n : names) {
+        if (hiprtcAddNameExpression(prog, n.c_str()) != HIPRTC_SUCCESS) {
+            hiprtcDestroyProgram(&prog);
+            return fail(FF_E_DEVICE, "hiprtcAddNameExpression failed for " + n);
+        }
+    }
     const std::string arch_opt = "--offload-arch=" + arch;
     const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
