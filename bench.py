@@ -453,12 +453,17 @@ def extended(A, I, torch, np):
         wc_expr = A.System.from_exprs(["1/(1+exp(-(p4*(fma(p0, x0, fma(-p1, x1, p8)) - p5)))) - x0",
                                        "1/(1+exp(-(p6*(fma(p2, x0, fma(-p3, x1, p9)) - p7)))) - x1"], wc.params)
         wc_builtin = A.System("wilson_cowan", 2, wc.params)
+        wc_fast = A.System.from_exprs(["1/(1+exp(-(p4*(fma(p0, x0, fma(-p1, x1, p8)) - p5)))) - x0",
+                                       "1/(1+exp(-(p6*(fma(p2, x0, fma(-p3, x1, p9)) - p7)))) - x1"], wc.params,
+                                      fast_f32=True)
         for prec in ("fp32_kahan", "fp64"):
             dt_ = torch.float64 if prec == "fp64" else torch.float32
             x = torch.as_tensor(ew.state[:, :nf], dtype=dt_, device=dev).contiguous()
             p_ = torch.as_tensor(ew.pparams[:, :nf], dtype=dt_, device=dev).contiguous()
             out_ = {}
-            for name, sobj in (("builtin", wc_builtin), ("expr", wc_expr)):
+            for name, sobj in (("builtin", wc_builtin), ("expr", wc_expr), ("expr_fast_f32", wc_fast)):
+                if prec == "fp64" and name == "expr_fast_f32":
+                    continue
                 xs = x.clone()
                 c_ = torch.zeros_like(xs) if prec == "fp32_kahan" else None
 
@@ -468,6 +473,9 @@ def extended(A, I, torch, np):
                 ms = _time_stream(torch, go, reps=3)
                 out_[name] = {"ms": ms, "particle_steps_per_s": nf * wc.nsteps / (ms * 1e-3)}
             out_["expr_vs_builtin"] = out_["expr"]["particle_steps_per_s"] / out_["builtin"]["particle_steps_per_s"]
+            if "expr_fast_f32" in out_:
+                out_["expr_fast_f32_vs_builtin"] = (out_["expr_fast_f32"]["particle_steps_per_s"] /
+                                                    out_["builtin"]["particle_steps_per_s"])
             r[f"expr_wc_2m_forward_{prec}"] = out_
         return r
 

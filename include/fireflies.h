@@ -150,6 +150,11 @@ ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n
  * fabs (one argument), pow fmin fmax (two), fma (three: a*b+c rounded once).
  * Every operation rounds to the working precision (no contraction, no fast
  * math; the device math library's functions for the named functions).
+ * flags: 0, or FF_EXPR_FAST_F32: in single precision exp(x) is the hardware
+ * 2^(x log2 e) and a / b is a * rcp(b) (about 1 ulp each: the single-precision
+ * policy of the built-in systems) instead of the library expf and a correctly
+ * rounded division; double precision is not affected.  Unknown bits:
+ * FF_E_INVALID.
  * dim 1..15, n_params 0..16 (params: host array, copied; may be NULL when
  * n_params == 0), at most 65536 characters per expression, 256 levels of
  * nesting and 4096 distinct operations per system.  A syntax error returns
@@ -161,8 +166,9 @@ ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n
  * The adjoint and the ragged-batch calls (ff_integrate_groups,
  * ff_autotune) hold compiled-in right-hand sides only and return
  * FF_E_UNSUPPORTED for such a system. */
+#define FF_EXPR_FAST_F32 1u
 ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n_params,
-                                const double* params, ff_system_t* out);
+                                const double* params, uint32_t flags, ff_system_t* out);
 
 /* Compile the kernels of an expression system for precision prec (ff_prec).
  * arch == NULL: for the current device, and load them there (do this before

@@ -16,6 +16,7 @@ FF_OK, FF_E_INVALID, FF_E_UNSUPPORTED, FF_E_NOMEM, FF_E_DEVICE = range(5)
 FF_FP32, FF_FP32_KAHAN, FF_FP64 = 0, 1, 2
 FF_RHS_LINEAR, FF_RHS_LORENZ, FF_RHS_WILSON_COWAN, FF_RHS_HH_RING = 0, 1, 2, 3
 FF_RHS_EXPR = 16
+FF_EXPR_FAST_F32 = 1
 FF_MAX_PP = 4
 ABI_VERSION = 1
 
@@ -61,7 +62,8 @@ SIGNATURES = {
     "ff_system_set_params": (_i32, [_vp, _c.POINTER(_dbl), _i32]),
     "ff_system_get_params": (_i32, [_vp, _c.POINTER(_dbl), _i32]),
     "ff_system_info": (_i32, [_vp, _c.POINTER(_i32), _c.POINTER(_i32), _c.POINTER(_i32)]),
-    "ff_system_create_expr": (_i32, [_i32, _c.POINTER(_c.c_char_p), _i32, _c.POINTER(_dbl), _c.POINTER(_vp)]),
+    "ff_system_create_expr": (_i32, [_i32, _c.POINTER(_c.c_char_p), _i32, _c.POINTER(_dbl), _c.c_uint32,
+                                     _c.POINTER(_vp)]),
     "ff_system_compile": (_i32, [_vp, _i32, _c.c_char_p]),
     "ff_system_source": (_i32, [_vp, _i32, _c.c_char_p, _sz, _c.POINTER(_sz)]),
     "ff_integrate": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Tuning), _vp]),

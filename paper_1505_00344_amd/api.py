@@ -44,14 +44,16 @@ class System:
         self.n_params = len(params)
 
     @classmethod
-    def from_exprs(cls, exprs: Sequence[str], params: Sequence[float] = ()) -> "System":
+    def from_exprs(cls, exprs: Sequence[str], params: Sequence[float] = (), fast_f32: bool = False) -> "System":
         """A system whose right-hand side is given as text (ff_system_create_expr):
-        ``exprs[d]`` is x_d' over ``x0..`` and ``p0..``."""
+        ``exprs[d]`` is x_d' over ``x0..`` and ``p0..``; ``fast_f32`` selects the
+        hardware exp and reciprocal in single precision."""
         self = cls.__new__(cls)
         arr = (ctypes.c_char_p * len(exprs))(*[e.encode() for e in exprs])
         p = (ctypes.c_double * max(len(params), 1))(*map(float, params))
         h = ctypes.c_void_p()
-        call("ff_system_create_expr", len(exprs), arr, len(params), p, ctypes.byref(h))
+        call("ff_system_create_expr", len(exprs), arr, len(params), p, _ffi.FF_EXPR_FAST_F32 if fast_f32 else 0,
+             ctypes.byref(h))
         self.handle = h
         self.rhs = FF_RHS_EXPR
         self.dim = len(exprs)

@@ -23,6 +23,10 @@
 // (the code is compiled without contraction and without fast math), so the
 // tree fixes the result up to the accuracy of the device math library.
 //
+// With FF_EXPR_FAST_F32, single precision evaluates exp(x) as the hardware
+// 2^(x log2 e) and a / b as a * rcp(b) (about 1 ulp each, the built-in
+// systems' single-precision policy); everything else is unchanged.
+//
 // Two rewrites that leave every value unchanged: identical subtrees are
 // evaluated once, and subtrees that depend on parameters and literals only
 // are evaluated once per particle (the system's derived constants q) instead
@@ -272,6 +276,7 @@ std::string literal(uint64_t bits, bool f32) {
 
 struct ExprProgram {
     int dim = 0, np = 0;
+    uint32_t flags = 0;
     std::vector<std::string> text;  // the expressions as given
     Dag dag;
     std::vector<int> roots;
@@ -302,6 +307,7 @@ struct ExprProgram {
 // The kernel source of one precision: system struct + explicit instances.
 std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>* names) {
     const bool f32 = prec != FF_FP64;
+    const bool fast = f32 && (P.flags & FF_EXPR_FAST_F32);
     const char* R = f32 ? "float" : "double";
     const std::vector<Node>& N = P.dag.nodes;
     // which state-free internal nodes does the per-step code (or a root) use?
@@ -337,8 +343,10 @@ std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>
             case kAdd: return a + " + " + b;
             case kSub: return a + " - " + b;
             case kMul: return a + " * " + b;
-            case kDiv: return a + " / " + b;
+            case kDiv: return fast ? a + " * __builtin_amdgcn_rcpf(" + b + ")" : a + " / " + b;
             case kCall: {
+                if (fast && std::string(kFn[n.fn].name) == "exp")
+                    return "__builtin_amdgcn_exp2f(" + a + " * 0x1.715476p+0f)";
                 std::string s = std::string(f32 ? kFn[n.fn].f32 : kFn[n.fn].f64) + "(" + a;
                 for (int k = 1; k < kFn[n.fn].arity; ++k) s += ", " + ref(n.arg[k], in_f);
                 return s + ")";
@@ -351,7 +359,7 @@ std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>
     src += "// generated: fused RK4 step kernel for a user right-hand side\n";
     src += "#include \"ff_kernel.h\"\n\nnamespace ffx {\n\nstruct Sys {\n";
     src += "    static constexpr int D = " + std::to_string(P.dim) + ", NP = " + std::to_string(P.np > 0 ? P.np : 1) +
-           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ";\n";
+           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ";\n";
     src += std::string("    static __device__ __forceinline__ void derive(const ") + R + " (&p)[NP], " + R +
            " (&q)[NQ]) {\n        (void)p;\n";
     if (nq == 0) src += std::string("        q[0] = ") + R + "(0);\n";
@@ -506,10 +514,11 @@ using namespace ff;
 extern "C" {
 
 ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n_params, const double* params,
-                                ff_system_t* out) {
+                                uint32_t flags, ff_system_t* out) {
     set_error("");
     if (!out) return fail(FF_E_INVALID, "out is NULL");
     *out = nullptr;
+    if (flags & ~(uint32_t)FF_EXPR_FAST_F32) return fail(FF_E_INVALID, "unknown flags");
     if (dim < 1 || dim > kMaxDim) return fail(FF_E_INVALID, "dim must be in [1, 15]");
     if (n_params < 0 || n_params > kMaxParams) return fail(FF_E_INVALID, "n_params must be in [0, 16]");
     if (n_params > 0 && !params) return fail(FF_E_INVALID, "params is NULL");
@@ -518,6 +527,7 @@ ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n
     if (!P) return fail(FF_E_NOMEM, "out of host memory");
     P->dim = dim;
     P->np = n_params;
+    P->flags = flags;
     for (int d = 0; d < dim; ++d) {
         if (!exprs[d] || std::strlen(exprs[d]) > kMaxExprChars) {
             delete P;

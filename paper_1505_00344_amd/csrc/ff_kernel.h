@@ -213,9 +213,9 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
             nres[j] = rs->nres[idx[j]];
         }
     }
-    // two steps per trip for the small systems: the loop-carried state then
-    // needs no register copies (the large systems keep one step per trip)
-#pragma unroll(D <= 4 ? 2 : 1)
+    // steps per loop trip: each system's own measured choice (two lets the
+    // loop-carried state of Lorenz avoid register copies)
+#pragma unroll(S::UNROLL)
     for (int64_t s = 0; s < a.steps; ++s) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {

@@ -51,7 +51,24 @@ def test_size_limits(A, dim, npar, exprs, params):
     arr = (ctypes.c_char_p * max(len(exprs), 1))(*[e.encode() for e in exprs])
     p = (ctypes.c_double * max(len(params), 1))(*params)
     h = ctypes.c_void_p()
-    assert A._ffi.lib().ff_system_create_expr(dim, arr, npar, p, ctypes.byref(h)) == A._ffi.FF_E_INVALID
+    assert A._ffi.lib().ff_system_create_expr(dim, arr, npar, p, 0, ctypes.byref(h)) == A._ffi.FF_E_INVALID
+
+
+def test_unknown_flags_rejected(A):
+    arr = (ctypes.c_char_p * 1)(b"x0")
+    h = ctypes.c_void_p()
+    assert A._ffi.lib().ff_system_create_expr(1, arr, 0, None, 2, ctypes.byref(h)) == A._ffi.FF_E_INVALID
+    assert A._ffi.lib().ff_system_create_expr(1, arr, 0, None, 1, ctypes.byref(h)) == 0
+    A._ffi.lib().ff_system_destroy(h)
+
+
+def test_fast_f32_source(A):
+    s = A.System.from_exprs(["exp(x0) / (1 + x1)", "x0 - x1"], fast_f32=True)
+    f32 = s.source("fp32")
+    assert "__builtin_amdgcn_exp2f(" in f32 and "__builtin_amdgcn_rcpf(" in f32 and "expf(" not in f32
+    f64 = s.source("fp64")
+    assert "exp(" in f64 and " / " in f64 and "amdgcn" not in f64
+    s.compile("fp32_kahan", arch="gfx950")
 
 
 def test_nesting_and_size_limits(A):

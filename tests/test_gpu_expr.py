@@ -198,3 +198,36 @@ def test_explicit_compile_then_many_systems(A, ora):
     got, _ = run(A, systems[0], x, 0.01, 100, torch.float64)
     assert np.array_equal(got, ora.expr_rk4(["-1*x0 + p0"], [2.0], x, 0.01, 100))
     del systems
+
+
+def test_fast_f32_flag(A, ora):
+    # without exp or division the flag changes nothing: identical bits
+    w = I.lorenz_4096()
+    e = I.generate(w)
+    x32 = e.state[:, :3072].astype(np.float32)
+    s = A.System.from_exprs(LORENZ_EXPR, w.params, fast_f32=True)
+    got, c = run(A, s, x32, 0.005, 300, torch.float32, kahan=True)
+    ref, cref = ora.expr_rk4_f32(LORENZ_EXPR, w.params, x32, 0.005, 300, kahan=True)
+    assert np.array_equal(got, ref) and np.array_equal(c, cref)
+    # Wilson-Cowan with the hardware exp and reciprocal: the FP32 bounds against FP64
+    wc = I.wilson_cowan_4m(n=20000)
+    ew = I.generate(wc)
+    nf = ew.counts[0]
+    x, pp = f32_inputs(ew.state[:, :nf]), f32_inputs(ew.pparams[:, :nf])
+    h = float(np.float32(0.01))
+    ref = ora.expr_rk4(WC_EXPR, wc.params, x, h, wc.nsteps, pp_slot=wc.pp_slot, pparams=pp)
+    s = A.System.from_exprs(WC_EXPR, wc.params, fast_f32=True)
+    got, _ = run(A, s, x.astype(np.float32), h, wc.nsteps, torch.float32, pp=pp.astype(np.float32),
+                 pp_slot=wc.pp_slot, kahan=True)
+    err = mixed_error(got, ref)
+    record("expr_wc_fast_fp32_kahan_vs_fp64", kahan=quantiles(err))
+    assert np.median(err) <= tol.KAHAN_WC_MEDIAN and np.quantile(err, 0.99) <= tol.KAHAN_WC_P99, quantiles(err)
+    # a rational system: divisions through the hardware reciprocal
+    rng = np.random.default_rng(21)
+    xr = f32_inputs(rng.uniform(-2, 2, (3, 3000)))
+    s = A.System.from_exprs(RATIONAL, [1.5, 0.7, 2.0], fast_f32=True)
+    got, _ = run(A, s, xr.astype(np.float32), 0.01, 300, torch.float32, kahan=True)
+    ref = ora.expr_rk4(RATIONAL, [1.5, 0.7, 2.0], xr, float(np.float32(0.01)), 300)
+    err = mixed_error(got, ref)
+    record("expr_rational_fast_fp32_kahan_vs_fp64", kahan=quantiles(err))
+    assert np.quantile(err, 0.99) <= 1e-5 and err.max() <= 1e-4, quantiles(err)
