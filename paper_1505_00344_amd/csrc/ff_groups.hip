@@ -78,8 +78,13 @@ template <typename R> using Lin2 = Linear<R, 2>;
 template <typename R> using Lin3 = Linear<R, 3>;
 template <typename R> using Lin4 = Linear<R, 4>;
 
+// The kernel holds every system's step, so its register count is set by the
+// largest (the three-neuron ring: 230 VGPRs uncapped in single precision, two
+// waves per SIMD for every system of the batch); single precision caps it at
+// three waves (168 VGPRs, one 8-byte spill).
 template <typename R, bool KAHAN, int PPT>
-__global__ void __launch_bounds__(256) k_groups(GroupTable tab, unsigned int* counter) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
+k_groups(GroupTable tab, unsigned int* counter) {
     constexpr int PH = PPT > 2 ? 2 : PPT;  // the rings run at most 2 particles per thread
     __shared__ int s_t;
     for (;;) {

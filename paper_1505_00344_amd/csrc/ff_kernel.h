@@ -215,7 +215,7 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
     }
     // steps per loop trip: each system's own measured choice (two lets the
     // loop-carried state of Lorenz avoid register copies)
-#pragma unroll(S::UNROLL)
+#pragma unroll S::UNROLL
     for (int64_t s = 0; s < a.steps; ++s) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -267,6 +267,14 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
 
 template <class S, typename R, bool KAHAN, int PPT>
 __global__ void __launch_bounds__(256) k_rk4(RK4Args a) {
+    rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
+}
+
+// The same kernel with the register budget capped so that at least W waves
+// share a SIMD (512 / W VGPRs): for systems whose step would otherwise hold
+// so many registers that too few waves remain to hide latency.
+template <class S, typename R, bool KAHAN, int PPT, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_rk4_w(RK4Args a) {
     rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
 }
 
