@@ -277,8 +277,10 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
  *   img[(iy W + ix) 3 + k] += rint(256 * (w * rgb_k))  (pixels outside skipped).
  * A 2D orthographic view is an mvp whose last row is (0, 0, 0, 1).  img:
  * device uint32 [height][width][3], fixed point with 8 fractional bits, exact
- * and independent of particle order; n_culled: device uint64 or NULL;
- * accumulate == 0 clears both first.  radius <= 64. */
+ * and independent of particle order; a channel's sum wraps modulo 2^32 (after
+ * 2^24 full-weight, full-colour hits of one pixel), so weight should keep the
+ * densest pixel below that; n_culled: device uint64 or NULL; accumulate == 0
+ * clears both first.  width * height <= 2^28, radius <= 64. */
 typedef struct {
     int32_t axis[3];
     double mvp[16];

@@ -359,7 +359,7 @@ std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>
     src += "// generated: fused RK4 step kernel for a user right-hand side\n";
     src += "#include \"ff_kernel.h\"\n\nnamespace ffx {\n\nstruct Sys {\n";
     src += "    static constexpr int D = " + std::to_string(P.dim) + ", NP = " + std::to_string(P.np > 0 ? P.np : 1) +
-           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ", MIN_WAVES_F32 = 0;\n";
+           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ";\n";
     src += std::string("    static __device__ __forceinline__ void derive(const ") + R + " (&p)[NP], " + R +
            " (&q)[NQ]) {\n        (void)p;\n";
     if (nq == 0) src += std::string("        q[0] = ") + R + "(0);\n";

@@ -78,13 +78,8 @@ template <typename R> using Lin2 = Linear<R, 2>;
 template <typename R> using Lin3 = Linear<R, 3>;
 template <typename R> using Lin4 = Linear<R, 4>;
 
-// The kernel holds every system's step, so its register count is set by the
-// largest (the three-neuron ring: 230 VGPRs uncapped in single precision, two
-// waves per SIMD for every system of the batch); single precision caps it at
-// three waves (168 VGPRs, one 8-byte spill).
 template <typename R, bool KAHAN, int PPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
-k_groups(GroupTable tab, unsigned int* counter) {
+__global__ void __launch_bounds__(256) k_groups(GroupTable tab, unsigned int* counter) {
     constexpr int PH = PPT > 2 ? 2 : PPT;  // the rings run at most 2 particles per thread
     __shared__ int s_t;
     for (;;) {
@@ -366,9 +361,12 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
     // work on copies so the caller's state is untouched
     std::vector<ff_group> copy(groups, groups + n_groups);
     std::vector<void*> owned;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     auto cleanup = [&]() {
-        hipStreamSynchronize(st);
-        for (void* p : owned) hipFree(p);
+        (void)hipStreamSynchronize(st);
+        for (void* p : owned) (void)hipFree(p);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
     };
     for (ff_group& g : copy) {
         if (g.b.n == 0) continue;
@@ -381,14 +379,35 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
                 return fail(FF_E_NOMEM, "ff_autotune: hipMalloc of a state copy failed");
             }
             owned.push_back(p);
-            hipMemcpyAsync(p, *field, bytes, hipMemcpyDeviceToDevice, st);
+            if (hipError_t e = hipMemcpyAsync(p, *field, bytes, hipMemcpyDeviceToDevice, st)) {
+                cleanup();
+                return device_fail(e, "ff_autotune: copy of the state");
+            }
             *field = p;
         }
     }
+    for (hipEvent_t& e : ev) {
+        if (hipError_t err = hipEventCreate(&e)) {
+            e = nullptr;
+            cleanup();
+            return device_fail(err, "ff_autotune: hipEventCreate");
+        }
+    }
     const int64_t tune_steps = std::min<int64_t>(nsteps, 200);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    // one candidate: a warm-up, then one timed run of tune_steps steps
+    auto trial = [&](const ff_tuning& t, float* ms) -> ff_status {
+        Prepared P;
+        if (ff_status s = prepare(copy.data(), n_groups, t, &P)) return s;
+        if (ff_status s = run_prepared(P, std::min<int64_t>(t.steps_per_launch, tune_steps), t, counter, cus, st))
+            return s;
+        if (hipError_t e = hipEventRecord(ev[0], st)) return device_fail(e, "ff_autotune: hipEventRecord");
+        if (ff_status s = run_prepared(P, tune_steps, t, counter, cus, st)) return s;
+        if (hipError_t e = hipEventRecord(ev[1], st)) return device_fail(e, "ff_autotune: hipEventRecord");
+        if (hipError_t e = hipEventSynchronize(ev[1])) return device_fail(e, "ff_autotune: hipEventSynchronize");
+        if (hipError_t e = hipEventElapsedTime(ms, ev[0], ev[1]))
+            return device_fail(e, "ff_autotune: hipEventElapsedTime");
+        return FF_OK;
+    };
     float best = 1e30f;
     ff_tuning bestt{(int32_t)std::min<int64_t>(nsteps, 500), 1, 256};
     const int64_t smax = std::min<int64_t>(500, nsteps);
@@ -396,21 +415,15 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
     for (int64_t s : {10, 20, 50, 100, 200, 500})
         if (s <= smax) svals.push_back(s);
     if (svals.empty() || svals.back() != smax) svals.push_back(smax);
-    ff_status status = FF_OK;
     for (int ppt : {1, 2, 4}) {
         for (int block : {128, 256}) {
             for (int64_t s : svals) {
-                ff_tuning t{(int32_t)s, ppt, block};
-                Prepared P;
-                if ((status = prepare(copy.data(), n_groups, t, &P)) != FF_OK) break;
-                // warm-up, then one timed run of tune_steps steps
-                run_prepared(P, std::min<int64_t>(s, tune_steps), t, counter, cus, st);
-                hipEventRecord(e0, st);
-                if ((status = run_prepared(P, tune_steps, t, counter, cus, st)) != FF_OK) break;
-                hipEventRecord(e1, st);
-                hipEventSynchronize(e1);
+                const ff_tuning t{(int32_t)s, ppt, block};
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (ff_status status = trial(t, &ms)) {
+                    cleanup();
+                    return status;
+                }
                 if (ms < best) {
                     best = ms;
                     bestt = t;
@@ -418,10 +431,7 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     cleanup();
-    if (status != FF_OK) return status;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = bestt;

@@ -270,14 +270,6 @@ __global__ void __launch_bounds__(256) k_rk4(RK4Args a) {
     rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
 }
 
-// The same kernel with the register budget capped so that at least W waves
-// share a SIMD (512 / W VGPRs): for systems whose step would otherwise hold
-// so many registers that too few waves remain to hide latency.
-template <class S, typename R, bool KAHAN, int PPT, int W>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_rk4_w(RK4Args a) {
-    rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
-}
-
 template <class S, typename R, bool KAHAN, int PPT>
 __global__ void __launch_bounds__(256) k_rk4_reset(RK4Args a, ResetArgs r) {
     rk4_tile<S, R, KAHAN, PPT, true>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT), &r);

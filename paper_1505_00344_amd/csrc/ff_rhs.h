@@ -4,8 +4,6 @@
 // Each system is a struct template over the working precision R with
 //   D   number of state components,  NP  number of parameters,
 //   UNROLL  RK4 steps per trip of the fused kernel's step loop,
-//   MIN_WAVES_F32  if > 0, the single-precision one-particle-per-thread
-//                  kernel caps its registers so that this many waves fit a SIMD,
 //   NQ  number of constants derived from the parameters once per particle,
 //   derive(p, q)                 fill q from p,
 //   f(p, q, x, out)              the right-hand side (autonomous: no t),
@@ -30,7 +28,7 @@ namespace ff {
 // ---------------------------------------------------------------- linear
 // x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.
 template <typename R, int Dm> struct Linear {
-    static constexpr int D = Dm, NP = Dm * Dm, NQ = 1, UNROLL = 2, MIN_WAVES_F32 = 0;
+    static constexpr int D = Dm, NP = Dm * Dm, NQ = 1, UNROLL = 2;
     static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
 #pragma unroll
@@ -56,7 +54,7 @@ template <typename R, int Dm> struct Linear {
 // ---------------------------------------------------------------- Lorenz
 // Section 2.2: x' = s (y - x), y' = x (r - z) - y, z' = x y - b z; p = [s, r, b].
 template <typename R> struct Lorenz {
-    static constexpr int D = 3, NP = 3, NQ = 1, UNROLL = 2, MIN_WAVES_F32 = 0;
+    static constexpr int D = 3, NP = 3, NQ = 1, UNROLL = 2;
     static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
         o[0] = p[0] * (x[1] - x[0]);
@@ -87,7 +85,7 @@ template <typename R> struct WilsonCowan {
     // round the same number of times as the canonical order, with errors of
     // the same size.)  Otherwise the canonical order below is kept.
     static constexpr bool kFold = M<R>::kFast;
-    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1, MIN_WAVES_F32 = 0;
+    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1;
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         if constexpr (kFold) {
             const R gE = -p[4] * R(kLog2e), gI = -p[6] * R(kLog2e);
@@ -191,9 +189,7 @@ __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg) {
 }
 
 template <typename R, int N> struct HHRing {
-    // the three-neuron compensated step holds 165 VGPRs (3 waves) uncapped;
-    // capped at 128 (4 waves) its loop is unchanged (spills only outside it)
-    static constexpr int D = 5 * N, NP = 14, NQ = 1, UNROLL = 1, MIN_WAVES_F32 = N == 3 ? 4 : 0;
+    static constexpr int D = 5 * N, NP = 14, NQ = 1, UNROLL = 1;
     static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
         const R invC = M<R>::rcp_(p[6]);

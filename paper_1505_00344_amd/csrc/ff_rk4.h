@@ -54,12 +54,8 @@ hipError_t launch_rk4_t(const RK4Launch& L) {
         }
         return hipErrorInvalidValue;  // the launcher clamps PPT to 2 for resets
     }
-    if constexpr (S::MIN_WAVES_F32 > 0 && sizeof(R) == 4 && PPT == 1)
-        hipLaunchKernelGGL((k_rk4_w<S, R, KAHAN, PPT, S::MIN_WAVES_F32>), dim3((unsigned)grid), dim3(L.block), 0,
-                           L.stream, make_args(L));
-    else
-        hipLaunchKernelGGL((k_rk4<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
-                           make_args(L));
+    hipLaunchKernelGGL((k_rk4<S, R, KAHAN, PPT>), dim3((unsigned)grid), dim3(L.block), 0, L.stream,
+                       make_args(L));
     return hipGetLastError();
 }
 
