@@ -21,6 +21,9 @@ ff_status fail(ff_status code, const std::string& msg) {
 }
 
 ff_status device_fail(hipError_t e, const char* where) {
+    // the error is reported here: clear the runtime's sticky last error so
+    // that the caller's next, unrelated HIP call does not report it again
+    (void)hipGetLastError();
     return fail(FF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 

@@ -370,7 +370,9 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
     };
     for (ff_group& g : copy) {
         if (g.b.n == 0) continue;
-        const size_t bytes = (size_t)g.sys->dim * g.b.ld * prec_size(g.b.prec);
+        // the slice's rows d*ld + [0, n) from its first particle: the span ends
+        // n elements into the last row, inside the caller's [dim][ld] array
+        const size_t bytes = ((size_t)(g.sys->dim - 1) * g.b.ld + g.b.n) * prec_size(g.b.prec);
         for (void** field : {&g.b.state, &g.b.comp}) {
             if (!*field) continue;
             void* p = nullptr;
