@@ -225,3 +225,35 @@ def test_mixed_batch_one_frame_on_sample(A, ora):
                 err = mixed_error(got[:, part].astype(np.float64), ref)
                 bound = tol.KAHAN_WC_P99 if w.system == I.WILSON_COWAN else tol.KAHAN_HH_MAX
                 assert np.quantile(err, 0.99) <= bound, (w.name, off, quantiles(err))
+
+
+@pytest.mark.parametrize("kahan", [False, True])
+def test_more_than_2_31_particles(A, ora, kahan):
+    # 64-bit particle indexing: 2^31 + 4096 particles (25.8 GB of FP32 state,
+    # drawn on the device from a seeded generator in the Lorenz box); the
+    # particles around index 2^31 and a random sample against the oracle
+    n = (1 << 31) + 4096
+    g = torch.Generator(device="cuda:0").manual_seed(20150501)
+    st = torch.rand((3, n), generator=g, device="cuda:0", dtype=torch.float32)
+    for d, (lo, hi) in enumerate(I.LORENZ_BOX):
+        st[d].mul_(hi - lo).add_(lo)
+    comp = torch.zeros_like(st) if kahan else None
+    rng = np.random.default_rng(5)
+    edge = (1 << 31)
+    idx = np.unique(np.concatenate([[0, 1, edge - 2, edge - 1, edge, edge + 1, n - 1],
+                                    rng.integers(0, n, 2000)]))
+    it = torch.as_tensor(idx, device="cuda:0")
+    x0 = st[:, it].cpu().numpy()
+    s = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    A.integrate(s, st, 0.005, 20, comp=comp)
+    torch.cuda.synchronize()
+    got = st[:, it].cpu().numpy()
+    ref, cref = ora.rk4_f32(ora.LORENZ, I.LORENZ_PARAMS, x0, 0.005, 20, kahan=kahan)
+    assert np.array_equal(got, ref)
+    if kahan:
+        assert np.array_equal(comp[:, it].cpu().numpy(), cref)
+    # one projection holds at most 2^31 - 1 particles: refused, nothing launched
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_UNSUPPORTED"):
+        A.project_histogram(s, st, 0, 2, (-20.0, 20.0), (0.0, 50.0), 64, 64)
+    del st, comp
+    torch.cuda.empty_cache()
