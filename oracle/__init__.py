@@ -76,8 +76,10 @@ def lib():
                                    ctypes.c_double, _i64]
         L.ffo_expr_rk4_f32.argtypes = [_int, _cpp, _dp, _int, _ip, _int, _fp, _fp, _fp, _i64,
                                        _i64, ctypes.c_float, _i64]
+        L.ffo_expr_rk4_dual.argtypes = [_int, _cpp, _dp, _int, _ip, _int, _dp, _dp, _dp, _dp, _dp,
+                                        _dp, _dp, _i64, _i64, ctypes.c_double, _i64]
         L.ffo_expr_error.restype = ctypes.c_char_p
-        for f in ("ffo_expr_rk4", "ffo_expr_rk4_f32", "ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32", "ffo_render",
+        for f in ("ffo_expr_rk4", "ffo_expr_rk4_f32", "ffo_expr_rk4_dual", "ffo_n_params", "ffo_rhs", "ffo_jacobians", "ffo_rk4", "ffo_rk4_f32", "ffo_render",
                   "ffo_rk4_cstep", "ffo_adjoint", "ffo_histogram", "ffo_philox4x32_10",
                   "ffo_rk4_reset", "ffo_rk4_reset_f32"):
             getattr(L, f).restype = _int
@@ -350,3 +352,25 @@ def expr_rk4_f32(exprs, params, state, h, nsteps, pp_slot=None, pparams=None, ka
                                        _ptr(pp, _fp), _ptr(st, _fp), _ptr(c, _fp), n, n,
                                        float(np.float32(h)), int(nsteps)))
     return st, c
+
+
+def expr_rk4_dual(exprs, params, x0, h, nsteps, pp_slot=None, pparams=None, dx0=None, dparams=None,
+                  dpp=None):
+    """FP64 expression map and its directional derivative: returns (xT, dxT)."""
+    x0 = _f64(x0)
+    dim, n = x0.shape
+    if len(exprs) != dim:
+        raise ValueError("one expression per state variable")
+    p = _f64(params)
+    slots, npp, pp = _pp(pp_slot, pparams, n, _f64)
+    dx0 = None if dx0 is None else _f64(dx0).reshape(dim, n)
+    dparams = None if dparams is None else _f64(dparams)
+    dpp = None if dpp is None else _f64(dpp).reshape(npp, n)
+    xT = np.empty_like(x0)
+    dxT = np.empty_like(x0)
+    ex, _keep = _exprs(exprs)
+    _expr_check(lib().ffo_expr_rk4_dual(dim, ex, _ptr(p, _dp), len(p), _ptr(slots, _ip), npp,
+                                        _ptr(pp, _dp), _ptr(x0, _dp), _ptr(dx0, _dp),
+                                        _ptr(dparams, _dp), _ptr(dpp, _dp), _ptr(xT, _dp),
+                                        _ptr(dxT, _dp), n, n, float(h), int(nsteps)))
+    return xT, dxT

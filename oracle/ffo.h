@@ -177,6 +177,16 @@ int ffo_expr_rk4_f32(int dim, const char* const* exprs, const double* params, in
                      const int32_t* pp_slot, int n_pp, const float* pparams, float* state,
                      float* comp, int64_t n, int64_t ld, float h, int64_t nsteps);
 const char* ffo_expr_error(void);
+/* The FP64 expression map with its directional derivative (forward-mode
+ * differentiation of every operation): inputs perturbed along dx0 (SoA like
+ * the state), dparams (n_params) and dpp (SoA like pparams), any of them NULL
+ * for zero.  xT equals ffo_expr_rk4's result; dxT is d xT along the direction.
+ * fabs has slope +1 at 0; fmin/fmax follow the returned argument (the first on
+ * a tie); pow's log term is dropped when the exponent's direction is zero. */
+int ffo_expr_rk4_dual(int dim, const char* const* exprs, const double* params, int n_params,
+                      const int32_t* pp_slot, int n_pp, const double* pparams, const double* x0,
+                      const double* dx0, const double* dparams, const double* dpp, double* xT,
+                      double* dxT, int64_t n, int64_t ld, double h, int64_t nsteps);
 
 #ifdef __cplusplus
 }

@@ -196,6 +196,73 @@ template <class T> T eval(const Node* n, const T* x, const T* p) {
     return T(0);
 }
 
+// Forward-mode derivative: a value and its derivative along one direction.
+// The value part follows exactly the operations of eval<double>; the
+// derivative part applies the chain rule to each operation.
+struct Dual {
+    double v, d;
+};
+
+Dual eval_dual(const Node* n, const Dual* x, const Dual* p) {
+    switch (n->kind) {
+        case Node::NUM: return {n->val, 0.0};
+        case Node::VAR: return x[n->index];
+        case Node::PAR: return p[n->index];
+        case Node::NEG: {
+            const Dual a = eval_dual(n->kids[0].get(), x, p);
+            return {-a.v, -a.d};
+        }
+        case Node::ADD:
+        case Node::SUB:
+        case Node::MUL:
+        case Node::DIV: {
+            const Dual a = eval_dual(n->kids[0].get(), x, p);
+            const Dual b = eval_dual(n->kids[1].get(), x, p);
+            if (n->kind == Node::ADD) return {a.v + b.v, a.d + b.d};
+            if (n->kind == Node::SUB) return {a.v - b.v, a.d - b.d};
+            if (n->kind == Node::MUL) return {a.v * b.v, a.d * b.v + a.v * b.d};
+            const double q = a.v / b.v;  // (a/b)' = (a' - q b') / b
+            return {q, (a.d - q * b.d) / b.v};
+        }
+        case Node::FUN: {
+            const Dual a = eval_dual(n->kids[0].get(), x, p);
+            switch (n->fn) {
+                case 0: { const double e = std::exp(a.v); return {e, e * a.d}; }
+                case 1: return {std::expm1(a.v), std::exp(a.v) * a.d};
+                case 2: return {std::log(a.v), a.d / a.v};
+                case 3: return {std::log1p(a.v), a.d / (1.0 + a.v)};
+                case 4: { const double r = std::sqrt(a.v); return {r, a.d / (2.0 * r)}; }
+                case 5: return {std::sin(a.v), std::cos(a.v) * a.d};
+                case 6: return {std::cos(a.v), -std::sin(a.v) * a.d};
+                case 7: { const double t = std::tan(a.v); return {t, (1.0 + t * t) * a.d}; }
+                case 8: { const double t = std::tanh(a.v); return {t, (1.0 - t * t) * a.d}; }
+                case 9: return {std::sinh(a.v), std::cosh(a.v) * a.d};
+                case 10: return {std::cosh(a.v), std::sinh(a.v) * a.d};
+                case 11: return {std::atan(a.v), a.d / (1.0 + a.v * a.v)};
+                case 12: return {std::fabs(a.v), a.v >= 0.0 ? a.d : -a.d};  // slope +1 at 0
+            }
+            const Dual b = eval_dual(n->kids[1].get(), x, p);
+            if (n->fn == kTernary) {
+                const Dual c = eval_dual(n->kids[2].get(), x, p);
+                return {std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d};
+            }
+            if (n->fn == 13) {
+                // d(a^b) = b a^(b-1) a' + a^b log(a) b'; a term whose direction is
+                // zero is left out (a constant exponent needs no log of a)
+                const double t = std::pow(a.v, b.v);
+                double d = 0.0;
+                if (a.d != 0.0) d += b.v * std::pow(a.v, b.v - 1.0) * a.d;
+                if (b.d != 0.0) d += t * std::log(a.v) * b.d;
+                return {t, d};
+            }
+            // fmin / fmax follow the argument they return (the first on a tie)
+            const double t = n->fn == 14 ? std::fmin(a.v, b.v) : std::fmax(a.v, b.v);
+            return {t, t == a.v ? a.d : b.d};
+        }
+    }
+    return {0.0, 0.0};
+}
+
 constexpr int kExprMaxDim = 16;
 constexpr int kExprMaxParams = 32;
 
@@ -286,8 +353,56 @@ int expr_rk4(int dim, const char* const* exprs, const double* params, int n_para
     }
     return 0;
 }
-
-
+// The FP64 map of expr_rk4 carried with its derivative along the directions
+// dx0 (state), dparams (global parameters) and dpp (per-particle parameters).
+int expr_rk4_dual(int dim, const char* const* exprs, const double* params, int n_params,
+                  const int32_t* pp_slot, int n_pp, const double* pparams, const double* x0,
+                  const double* dx0, const double* dparams, const double* dpp, double* xT, double* dxT,
+                  int64_t n, int64_t ld, double h, int64_t nsteps) {
+    if (dim < 1 || dim > kExprMaxDim || n_params < 0 || n_params > kExprMaxParams || n < 0 ||
+        ld < n || nsteps < 0 || n_pp < 0 || n_pp > 4 || (n_pp > 0 && !pp_slot) ||
+        (n_params > 0 && !params))
+        return -1;
+    for (int k = 0; k < n_pp; ++k)
+        if (pp_slot[k] < 0 || pp_slot[k] >= n_params) return -1;
+    ExprSystem sys;
+    if (!build(dim, n_params, exprs, &sys, &g_expr_err)) return -2;
+    const double h2 = h * 0.5, h6 = h / 6.0;
+    // y = fma(w, k, x) on duals: value fma(w, k.v, x.v), derivative w k.d + x.d
+    auto stage = [](double w, Dual k, Dual x) { return Dual{std::fma(w, k.v, x.v), w * k.d + x.d}; };
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        Dual p[kExprMaxParams], x[kExprMaxDim];
+        Dual k1[kExprMaxDim], k2[kExprMaxDim], k3[kExprMaxDim], k4[kExprMaxDim], y[kExprMaxDim];
+        for (int q = 0; q < n_params; ++q) p[q] = {params[q], dparams ? dparams[q] : 0.0};
+        for (int q = 0; q < n_pp; ++q)
+            p[pp_slot[q]] = {pparams[q * ld + i], dpp ? dpp[q * ld + i] : 0.0};
+        for (int d = 0; d < dim; ++d) x[d] = {x0[d * ld + i], dx0 ? dx0[d * ld + i] : 0.0};
+        auto f = [&](const Dual* at, Dual* out) {
+            for (int d = 0; d < dim; ++d) out[d] = eval_dual(sys.f[d].get(), at, p);
+        };
+        for (int64_t s = 0; s < nsteps; ++s) {
+            f(x, k1);
+            for (int d = 0; d < dim; ++d) y[d] = stage(h2, k1[d], x[d]);
+            f(y, k2);
+            for (int d = 0; d < dim; ++d) y[d] = stage(h2, k2[d], x[d]);
+            f(y, k3);
+            for (int d = 0; d < dim; ++d) y[d] = stage(h, k3[d], x[d]);
+            f(y, k4);
+            for (int d = 0; d < dim; ++d) {
+                Dual sum{k2[d].v + k3[d].v, k2[d].d + k3[d].d};
+                sum = {std::fma(2.0, sum.v, k1[d].v), 2.0 * sum.d + k1[d].d};
+                sum = {sum.v + k4[d].v, sum.d + k4[d].d};
+                x[d] = stage(h6, sum, x[d]);
+            }
+        }
+        for (int d = 0; d < dim; ++d) {
+            xT[d * ld + i] = x[d].v;
+            dxT[d * ld + i] = x[d].d;
+        }
+    }
+    return 0;
+}
 
 }  // namespace
 
@@ -307,6 +422,14 @@ int ffo_expr_rk4_f32(int dim, const char* const* exprs, const double* params, in
                      float* comp, int64_t n, int64_t ld, float h, int64_t nsteps) {
     return expr_rk4<float>(dim, exprs, params, n_params, pp_slot, n_pp, pparams, state, comp, n,
                            ld, h, nsteps);
+}
+
+int ffo_expr_rk4_dual(int dim, const char* const* exprs, const double* params, int n_params,
+                      const int32_t* pp_slot, int n_pp, const double* pparams, const double* x0,
+                      const double* dx0, const double* dparams, const double* dpp, double* xT,
+                      double* dxT, int64_t n, int64_t ld, double h, int64_t nsteps) {
+    return expr_rk4_dual(dim, exprs, params, n_params, pp_slot, n_pp, pparams, x0, dx0, dparams,
+                         dpp, xT, dxT, n, ld, h, nsteps);
 }
 
 }  // extern "C"

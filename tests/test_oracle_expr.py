@@ -125,3 +125,72 @@ def test_linear_system_equals_rk4_amplification(ora):
 def test_malformed_expressions_are_rejected(ora, text):
     with pytest.raises(ValueError):
         ora.expr_rk4([text, "x0", "x1"], [], np.zeros((3, 1)), 0.1, 1)
+
+
+# --- forward-mode derivative of the expression map (the adjoint's reference) ---
+
+def test_dual_value_part_is_the_map(ora):
+    x = lorenz_start(200)
+    P = I.LORENZ_PARAMS
+    a = ora.expr_rk4(LORENZ_EXPR, P, x, 0.004, 300)
+    b, _ = ora.expr_rk4_dual(LORENZ_EXPR, P, x, 0.004, 300, dx0=np.ones_like(x))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["lorenz", "wc"])
+def test_dual_derivative_equals_builtin_complex_step(ora, which):
+    # the same maps written as expressions; derivative along random directions
+    # of the state, the global parameters and a per-particle parameter
+    rng = np.random.default_rng(9)
+    if which == "lorenz":
+        exprs, sysid, P, x, h, n = LORENZ_EXPR, ora.LORENZ, I.LORENZ_PARAMS, lorenz_start(200), 0.004, 150
+        slots, pp = [1], rng.uniform(20, 30, (1, 200))
+    else:
+        w = I.wilson_cowan_4m(n=400)
+        e = I.generate(w)
+        exprs, sysid, P, x, h, n = WC_EXPR, ora.WILSON_COWAN, w.params, e.state, -0.01, 200
+        slots, pp = w.pp_slot, e.pparams
+    dx0 = rng.normal(size=x.shape)
+    dparams = rng.normal(size=len(P))
+    dpp = rng.normal(size=pp.shape)
+    _, want = ora.rk4_cstep(sysid, P, x, h, n, pp_slot=slots, pparams=pp, dx0=dx0, dparams=dparams, dpp=dpp)
+    _, got = ora.expr_rk4_dual(exprs, P, x, h, n, pp_slot=slots, pparams=pp, dx0=dx0, dparams=dparams, dpp=dpp)
+    scale = np.maximum(np.abs(want), 1e-3 * np.abs(want).max())
+    assert (np.abs(got - want) / scale).max() <= 1e-10
+
+
+INTEGRANDS = [  # each expression of QUAD_EXPRS as a function of time
+    math.exp, math.expm1, lambda t: math.log(1 + t), math.log1p, math.sin, math.cos, math.tan, math.tanh,
+    math.sinh, math.cosh, math.atan, lambda t: t ** 3, lambda t: 1 / (1 + t * t), lambda t: math.sqrt(1 + t),
+]
+
+
+def test_dual_derivative_of_every_function(ora):
+    # x_k(T) = x_k(0) + int_{t0}^{t0+T} g_k(t) dt, so d x_k(T) / d t0 = g_k(t0 + T) - g_k(t0);
+    # RK4 integrates g_k' by Simpson's rule (error ~h^4), which tests every derivative rule
+    t0, T, n = 0.1, 0.5, 100
+    x = np.zeros((15, 1))
+    x[0] = t0
+    dx0 = np.zeros((15, 1))
+    dx0[0] = 1.0
+    _, d = ora.expr_rk4_dual(quad_system(), [], x, T / n, n, dx0=dx0)
+    assert d[0, 0] == 1.0
+    for k, (text, g) in enumerate(zip(QUAD_EXPRS, INTEGRANDS), start=1):
+        assert d[k, 0] == pytest.approx(g(t0 + T) - g(t0), rel=1e-9, abs=1e-12), text
+
+
+@pytest.mark.parametrize("exprs,params", [
+    (["pow(fabs(x1) + 1, p0) - x0", "fmin(x0, p1) - fmax(x1, -p1) * 0.5"], [1.5, 0.3]),
+    (["x1 / (1 + x0*x0)", "-p0 * x0 + p1 * fma(x0, x1, -x1)"], [0.8, 0.4]),
+])
+def test_dual_derivative_against_central_differences(ora, exprs, params):
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1.5, 1.5, (2, 64))
+    dx0 = rng.normal(size=x.shape)
+    dparams = rng.normal(size=len(params))
+    _, d = ora.expr_rk4_dual(exprs, params, x, 0.01, 100, dx0=dx0, dparams=dparams)
+    eps = 1e-6
+    xp = ora.expr_rk4(exprs, np.add(params, eps * dparams), x + eps * dx0, 0.01, 100)
+    xm = ora.expr_rk4(exprs, np.subtract(params, eps * dparams), x - eps * dx0, 0.01, 100)
+    fd = (xp - xm) / (2 * eps)
+    assert np.abs(d - fd).max() <= 1e-6 * max(1.0, np.abs(fd).max())

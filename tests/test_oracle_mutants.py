@@ -65,6 +65,15 @@ MUTANTS_EXPR = {
     "expr_pp_slot": ("for (int q = 0; q < n_pp; ++q) p[pp_slot[q]] = pparams[q * ld + i];",
                      "for (int q = 0; q < n_pp; ++q) p[q] = pparams[q * ld + i];"),
     "expr_kahan_sign": ("c[d] = (t - x[d]) - yk;", "c[d] = (t - x[d]) + yk;"),
+    "dual_cos_sign": ("case 6: return {std::cos(a.v), -std::sin(a.v) * a.d};",
+                      "case 6: return {std::cos(a.v), std::sin(a.v) * a.d};"),
+    "dual_quotient_rule": ("return {q, (a.d - q * b.d) / b.v};", "return {q, (a.d + q * b.d) / b.v};"),
+    "dual_fma_addend": ("return {std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d};",
+                        "return {std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d};"),
+    "dual_pow_exponent": ("if (b.d != 0.0) d += t * std::log(a.v) * b.d;", "if (b.d != 0.0) d += t * b.d;"),
+    "dual_stage_weight": ("return Dual{std::fma(w, k.v, x.v), w * k.d + x.d};",
+                          "return Dual{std::fma(w, k.v, x.v), k.d + x.d};"),
+    "dual_fmin_route": ("return {t, t == a.v ? a.d : b.d};", "return {t, t == a.v ? b.d : a.d};"),
 }
 
 
