@@ -446,6 +446,30 @@ def extended(A, I, torch, np):
         ex["vs_builtin"] = ex["particle_steps_per_s"] / plain["particle_steps_per_s"]
         ex["compile_s"] = compile_s
         r["expr_lorenz_8m_fp32_kahan"] = ex
+        # adjoint of mean z(T) w.r.t. each r_i over 200 steps (K = 50), FP64: generated
+        # vector-Jacobian products vs the built-in ones
+        adj = {}
+        x64 = torch.as_tensor(e.state, dtype=torch.float64, device=dev)
+        p64 = torch.as_tensor(e.pparams, dtype=torch.float64, device=dev).contiguous()
+        for name, sobj in (("builtin", builtin), ("expr", lorenz_expr)):
+            xs = x64.clone()
+            nb = A.adjoint_workspace_size(sobj, xs, 200, 50, pparams=p64, pp_slot=w.pp_slot)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            A.integrate_checkpointed(sobj, xs, 0.005, 200, 50, ws, pparams=p64, pp_slot=w.pp_slot)
+            lam = torch.zeros_like(xs)
+            mu = torch.empty_like(p64)
+
+            def back():
+                lam.zero_()
+                lam[2].fill_(1.0 / n)
+                A.adjoint(sobj, xs, 0.005, 200, 50, ws, lam, mu=mu, pparams=p64, pp_slot=w.pp_slot)
+            back()
+            ms = _time_stream(torch, back, reps=3)
+            adj[name] = {"reverse_ms": ms, "adjoint_steps_per_s": n * 200 / (ms * 1e-3)}
+            del ws, lam, mu, xs
+        adj["expr_vs_builtin"] = adj["expr"]["adjoint_steps_per_s"] / adj["builtin"]["adjoint_steps_per_s"]
+        r["expr_lorenz_8m_adjoint_fp64"] = adj
+        del x64, p64
         del st, comp, st0, pp, age, nres
         wc = I.wilson_cowan_4m()
         ew = I.generate(wc)

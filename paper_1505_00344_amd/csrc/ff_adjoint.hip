@@ -20,7 +20,14 @@
 
 namespace ff {
 
-int adj_tape_len(int rhs) { return rhs == FF_RHS_HH_RING ? 1 : 8; }
+// The 15-variable ring (and expression systems of more than four variables)
+// keep one step on the tape and recompute stage points (LOWREG); the small
+// systems keep eight.
+int adj_tape_len(const ff_system_s* sys) {
+    if (sys->rhs == FF_RHS_HH_RING) return 1;
+    if (sys->rhs == FF_RHS_EXPR) return sys->dim <= 4 ? 8 : 1;
+    return 8;
+}
 
 namespace {
 
@@ -35,7 +42,7 @@ AdjLayout adj_layout(const ff_system_s* sys, const ff_batch* b, int64_t nsteps, 
     AdjLayout L{};
     const size_t esz = prec_size(b->prec);
     const bool kahan = b->prec == FF_FP32_KAHAN;
-    const int64_t T = adj_tape_len(sys->rhs);
+    const int64_t T = adj_tape_len(sys);
     L.nseg = nsteps > 0 ? (nsteps + K - 1) / K : 0;
     const int64_t seg = nsteps < K ? nsteps : K;
     L.nsub = seg > 0 ? (seg + T - 1) / T : 0;
@@ -87,8 +94,6 @@ hipError_t zero_async(void* p, int64_t bytes, hipStream_t st) {
 
 ff_status check_adj_args(const ff_system_s* sys, const ff_batch* b, double dt, int64_t nsteps, int32_t K) {
     if (ff_status s = check_system(sys)) return s;
-    if (sys->expr)
-        return fail(FF_E_UNSUPPORTED, "the adjoint needs the built-in right-hand sides' vector-Jacobian products");
     if (ff_status s = check_batch(sys, b, false)) return s;
     if (nsteps < 0) return fail(FF_E_INVALID, "nsteps < 0");
     if (K < 1) return fail(FF_E_INVALID, "K must be >= 1");
@@ -122,6 +127,9 @@ ff_status ff_integrate_checkpointed(ff_system_t sys, const ff_batch* b, double d
     const AdjLayout W = adj_layout(sys, b, nsteps, K);
     if (!workspace || workspace_bytes < W.total)
         return fail(FF_E_NOMEM, "adjoint workspace too small: need " + std::to_string(W.total) + " bytes");
+    if (sys->expr) {
+        if (ff_status s = expr_prepare(sys, b->prec, kExprForward)) return s;
+    }
     const ff_tuning t = default_tuning(sys, b->prec, K);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
     const size_t st = (size_t)sys->dim * (size_t)b->n * prec_size(b->prec);
@@ -158,6 +166,9 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
     const AdjLayout W = adj_layout(sys, b, nsteps, K);
     if (!workspace || workspace_bytes < W.total)
         return fail(FF_E_NOMEM, "adjoint workspace too small: need " + std::to_string(W.total) + " bytes");
+    if (sys->expr) {
+        if (ff_status s = expr_prepare(sys, b->prec, kExprAdjoint)) return s;
+    }
     const ff_tuning t = default_tuning(sys, b->prec, K);
     AdjLaunch A;
     std::memset(&A, 0, sizeof A);
@@ -188,6 +199,7 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
             case FF_RHS_LORENZ: e = launch_adj_lorenz(A); break;
             case FF_RHS_WILSON_COWAN: e = launch_adj_wc(A); break;
             case FF_RHS_HH_RING: e = launch_adj_hh(sys->dim / 5, A); break;
+            case FF_RHS_EXPR: e = launch_adj_expr(sys, A); break;
             default: e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return device_fail(e, "ff_adjoint launch");

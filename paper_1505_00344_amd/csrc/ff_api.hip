@@ -215,7 +215,7 @@ ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int
     if (!std::isfinite(dt_signed)) return fail(FF_E_INVALID, "dt_signed is not finite");
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
     if (sys->expr) {
-        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+        if (ff_status s = expr_prepare(sys, b->prec, kExprForward)) return s;
     }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
@@ -286,7 +286,7 @@ extern "C" ff_status ff_integrate_reset(ff_system_t sys, const ff_batch* b, doub
     if (ff_status s = fill_reset(sys, b, reset, &r)) return s;
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
     if (sys->expr) {
-        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+        if (ff_status s = expr_prepare(sys, b->prec, kExprForward)) return s;
     }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);
@@ -311,7 +311,7 @@ extern "C" ff_status ff_integrate_record(ff_system_t sys, const ff_batch* b, dou
     }
     if (b->n == 0 || nsteps == 0 || dt_signed == 0.0) return FF_OK;
     if (sys->expr) {
-        if (ff_status s = expr_prepare(sys, b->prec)) return s;
+        if (ff_status s = expr_prepare(sys, b->prec, kExprForward)) return s;
     }
     const ff_tuning t = tuning ? *tuning : default_tuning(sys, b->prec, nsteps);
     RK4Launch L = make_launch(sys, b, dt_signed, &t, (hipStream_t)stream);

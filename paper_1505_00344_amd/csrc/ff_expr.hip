@@ -48,6 +48,7 @@
 
 #include "ff_embedded_src.h"
 #include "ff_internal.h"
+#include "ff_adjoint.h"
 #include "ff_rk4.h"
 
 namespace ff {
@@ -285,7 +286,7 @@ struct ExprProgram {
         hipModule_t mod = nullptr;
         hipFunction_t fn[kExprKernels] = {};
     };
-    std::map<std::pair<int, int>, Module> modules;  // (device, prec)
+    std::map<std::tuple<int, int, int>, Module> modules;  // (device, prec, kind)
 
     // Unloading a code object while its kernels are queued or running is
     // undefined, so each device is drained first (destroying a system is rare).
@@ -295,7 +296,7 @@ struct ExprProgram {
         const bool have = hipGetDevice(&cur) == hipSuccess;
         for (auto& kv : modules) {
             if (!kv.second.mod) continue;
-            if (hipSetDevice(kv.first.first) == hipSuccess) {
+            if (hipSetDevice(std::get<0>(kv.first)) == hipSuccess) {
                 (void)hipDeviceSynchronize();
                 (void)hipModuleUnload(kv.second.mod);
             }
@@ -304,15 +305,19 @@ struct ExprProgram {
     }
 };
 
-// The kernel source of one precision: system struct + explicit instances.
-std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>* names) {
+// The system struct of one precision: derive (state-free subtrees, once per
+// particle), f (the right-hand side) and vjp (its vector-Jacobian product by
+// reverse-mode differentiation of the DAG: node values forward, then node
+// adjoints in reverse order, each operation passing its local partials to
+// its operands).
+std::string expr_struct(const ExprProgram& P, int prec) {
     const bool f32 = prec != FF_FP64;
     const bool fast = f32 && (P.flags & FF_EXPR_FAST_F32);
     const char* R = f32 ? "float" : "double";
     const std::vector<Node>& N = P.dag.nodes;
+    auto internal = [&](int id) { return N[id].op != kNum && N[id].op != kX && N[id].op != kP; };
     // which state-free internal nodes does the per-step code (or a root) use?
     std::vector<char> need_q(N.size(), 0);
-    auto internal = [&](int id) { return N[id].op != kNum && N[id].op != kX && N[id].op != kP; };
     for (size_t i = 0; i < N.size(); ++i) {
         if (!N[i].varying) continue;
         for (int a : N[i].arg)
@@ -324,20 +329,30 @@ std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>
     int nq = 0;
     for (size_t i = 0; i < N.size(); ++i)
         if (need_q[i]) qslot[i] = nq++;
-
-    // operand text inside derive() (const temps c<i>) and inside f() (t<i>)
-    auto ref = [&](int id, bool in_f) -> std::string {
+    // operand text: in derive() state-free temps are c<i>; in f() the varying
+    // ones are t<i> and the state-free ones q[...]; in vjp() every internal
+    // node is a local v<i>
+    enum { kDerive, kF, kVjp };
+    auto ref = [&](int id, int where) -> std::string {
         const Node& n = N[id];
         if (n.op == kNum) return literal(n.bits, f32);
         if (n.op == kX) return "x[" + std::to_string(n.idx) + "]";
         if (n.op == kP) return "p[" + std::to_string(n.idx) + "]";
-        if (in_f && !n.varying) return "q[" + std::to_string(qslot[id]) + "]";
-        return (in_f ? "t" : "c") + std::to_string(id);
+        if (where == kF && !n.varying) return "q[" + std::to_string(qslot[id]) + "]";
+        return (where == kF ? "t" : where == kDerive ? "c" : "v") + std::to_string(id);
     };
-    auto expr_of = [&](int id, bool in_f) -> std::string {
+    auto fname = [&](const char* name) -> std::string {
+        for (const FnInfo& f : kFn)
+            if (std::strcmp(f.name, name) == 0) return f32 ? f.f32 : f.f64;
+        return name;
+    };
+    auto div = [&](const std::string& a, const std::string& b) {
+        return fast ? "(" + a + ") * __builtin_amdgcn_rcpf(" + b + ")" : "(" + a + ") / (" + b + ")";
+    };
+    auto expr_of = [&](int id, int where) -> std::string {
         const Node& n = N[id];
-        const std::string a = n.arg[0] >= 0 ? ref(n.arg[0], in_f) : "";
-        const std::string b = n.arg[1] >= 0 ? ref(n.arg[1], in_f) : "";
+        const std::string a = n.arg[0] >= 0 ? ref(n.arg[0], where) : "";
+        const std::string b = n.arg[1] >= 0 ? ref(n.arg[1], where) : "";
         switch (n.op) {
             case kNeg: return "-" + a;
             case kAdd: return a + " + " + b;
@@ -348,68 +363,148 @@ std::string expr_source(const ExprProgram& P, int prec, std::vector<std::string>
                 if (fast && std::string(kFn[n.fn].name) == "exp")
                     return "__builtin_amdgcn_exp2f(" + a + " * 0x1.715476p+0f)";
                 std::string s = std::string(f32 ? kFn[n.fn].f32 : kFn[n.fn].f64) + "(" + a;
-                for (int k = 1; k < kFn[n.fn].arity; ++k) s += ", " + ref(n.arg[k], in_f);
+                for (int k = 1; k < kFn[n.fn].arity; ++k) s += ", " + ref(n.arg[k], where);
                 return s + ")";
             }
         }
         return "";
     };
 
-    std::string src;
-    src += "// generated: fused RK4 step kernel for a user right-hand side\n";
-    src += "#include \"ff_kernel.h\"\n\nnamespace ffx {\n\nstruct Sys {\n";
+    std::string src = "namespace ffx {\n\nstruct Sys {\n";
+    src += std::string("    using R = ") + R + ";\n";
     src += "    static constexpr int D = " + std::to_string(P.dim) + ", NP = " + std::to_string(P.np > 0 ? P.np : 1) +
            ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ";\n";
-    src += std::string("    static __device__ __forceinline__ void derive(const ") + R + " (&p)[NP], " + R +
-           " (&q)[NQ]) {\n        (void)p;\n";
-    if (nq == 0) src += std::string("        q[0] = ") + R + "(0);\n";
+    src += "    static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {\n        (void)p;\n";
+    if (nq == 0) src += "        q[0] = R(0);\n";
     for (size_t i = 0; i < N.size(); ++i) {
         if (N[i].varying || !internal((int)i)) continue;
-        src += std::string("        const ") + R + " c" + std::to_string(i) + " = " + expr_of((int)i, false) + ";\n";
+        src += "        const R c" + std::to_string(i) + " = " + expr_of((int)i, kDerive) + ";\n";
         if (need_q[i]) src += "        q[" + std::to_string(qslot[i]) + "] = c" + std::to_string(i) + ";\n";
     }
     src += "    }\n";
-    src += std::string("    static __device__ __forceinline__ void f(const ") + R + " (&p)[NP], const " + R +
-           " (&q)[NQ], const " + R + " (&x)[D], " + R + " (&o)[D]) {\n        (void)p; (void)q; (void)x;\n";
+    src += "    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], "
+           "R (&o)[D]) {\n        (void)p; (void)q; (void)x;\n";
     for (size_t i = 0; i < N.size(); ++i) {
         if (!N[i].varying || !internal((int)i)) continue;
-        src += std::string("        const ") + R + " t" + std::to_string(i) + " = " + expr_of((int)i, true) + ";\n";
+        src += "        const R t" + std::to_string(i) + " = " + expr_of((int)i, kF) + ";\n";
     }
-    for (int d = 0; d < P.dim; ++d) src += "        o[" + std::to_string(d) + "] = " + ref(P.roots[d], true) + ";\n";
-    src += "    }\n};\n\n}  // namespace ffx\n\n";
-    // the host packs these structs: their sizes must agree
+    for (int d = 0; d < P.dim; ++d) src += "        o[" + std::to_string(d) + "] = " + ref(P.roots[d], kF) + ";\n";
+    src += "    }\n";
+
+    // vjp: gx += J^T a, gp += (df/dp)^T a.  A node is active if it depends on
+    // a state variable or a parameter; only active operands receive adjoints.
+    std::vector<char> act(N.size(), 0);
+    for (size_t i = 0; i < N.size(); ++i) {
+        act[i] = N[i].op == kX || N[i].op == kP;
+        for (int a : N[i].arg)
+            if (a >= 0 && act[a]) act[i] = 1;
+    }
+    src += "    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], "
+           "const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {\n        (void)p; (void)q; (void)x; (void)a; (void)gx; "
+           "(void)gp;\n";
+    for (size_t i = 0; i < N.size(); ++i)
+        if (internal((int)i)) src += "        const R v" + std::to_string(i) + " = " + expr_of((int)i, kVjp) + ";\n";
+    for (size_t i = 0; i < N.size(); ++i)
+        if (internal((int)i) && act[i]) src += "        R b" + std::to_string(i) + " = R(0);\n";
+    // contribution c to the adjoint of operand `id`
+    auto add = [&](int id, const std::string& c) -> std::string {
+        if (id < 0 || !act[id]) return "";
+        const Node& n = N[id];
+        if (n.op == kX) return "        gx[" + std::to_string(n.idx) + "] += " + c + ";\n";
+        if (n.op == kP) return "        gp[" + std::to_string(n.idx) + "] += " + c + ";\n";
+        return "        b" + std::to_string(id) + " += " + c + ";\n";
+    };
+    for (int d = 0; d < P.dim; ++d) src += add(P.roots[d], "a[" + std::to_string(d) + "]");
+    for (int i = (int)N.size() - 1; i >= 0; --i) {
+        if (!internal(i) || !act[i]) continue;
+        const Node& n = N[i];
+        const std::string B = "b" + std::to_string(i), t = ref(i, kVjp);
+        const int ia = n.arg[0], ib = n.arg[1], ic = n.arg[2];
+        const std::string va = ia >= 0 ? ref(ia, kVjp) : "", vb = ib >= 0 ? ref(ib, kVjp) : "";
+        switch (n.op) {
+            case kNeg: src += add(ia, "-" + B); break;
+            case kAdd: src += add(ia, B) + add(ib, B); break;
+            case kSub: src += add(ia, B) + add(ib, "-" + B); break;
+            case kMul: src += add(ia, B + " * " + vb) + add(ib, B + " * " + va); break;
+            case kDiv: src += add(ia, div(B, vb)) + add(ib, "-" + div(B + " * " + t, vb)); break;
+            case kCall: {
+                const std::string f = kFn[n.fn].name;
+                if (f == "exp") src += add(ia, B + " * " + t);
+                else if (f == "expm1") src += add(ia, B + " * (" + t + " + R(1))");
+                else if (f == "log") src += add(ia, div(B, va));
+                else if (f == "log1p") src += add(ia, div(B, "R(1) + " + va));
+                else if (f == "sqrt") src += add(ia, div(B, "R(2) * " + t));
+                else if (f == "sin") src += add(ia, B + " * " + fname("cos") + "(" + va + ")");
+                else if (f == "cos") src += add(ia, "-" + B + " * " + fname("sin") + "(" + va + ")");
+                else if (f == "tan") src += add(ia, B + " * (R(1) + " + t + " * " + t + ")");
+                else if (f == "tanh") src += add(ia, B + " * (R(1) - " + t + " * " + t + ")");
+                else if (f == "sinh") src += add(ia, B + " * " + fname("cosh") + "(" + va + ")");
+                else if (f == "cosh") src += add(ia, B + " * " + fname("sinh") + "(" + va + ")");
+                else if (f == "atan") src += add(ia, div(B, "R(1) + " + va + " * " + va));
+                else if (f == "fabs") src += add(ia, "(" + va + " >= R(0) ? " + B + " : -" + B + ")");  // slope +1 at 0
+                else if (f == "pow")
+                    src += add(ia, B + " * " + vb + " * " + fname("pow") + "(" + va + ", " + vb + " - R(1))") +
+                           add(ib, B + " * " + t + " * " + fname("log") + "(" + va + ")");
+                else if (f == "fmin" || f == "fmax")  // the returned operand (the first on a tie)
+                    src += add(ia, "(" + t + " == " + va + " ? " + B + " : R(0))") +
+                           add(ib, "(" + t + " == " + va + " ? R(0) : " + B + ")");
+                else if (f == "fma")
+                    src += add(ia, B + " * " + vb) + add(ib, B + " * " + va) + add(ic, B);
+                break;
+            }
+        }
+    }
+    src += "    }\n};\n\n}  // namespace ffx\n";
+    return src;
+}
+
+// The program of one precision and kind: the kernel skeleton, the system
+// struct, layout checks of the argument structs the host packs, and the
+// kernel instances requested by name.
+std::string expr_program(const ExprProgram& P, int prec, int kind, std::vector<std::string>* names) {
+    const char* R = prec == FF_FP64 ? "double" : "float";
+    const std::string K = prec == FF_FP32_KAHAN ? "true" : "false";
+    std::string src = "// generated: fused RK4 kernels for a user right-hand side\n";
+    src += kind == kExprAdjoint ? "#include \"ff_adjoint_kernel.h\"\n\n" : "#include \"ff_kernel.h\"\n\n";
+    src += expr_struct(P, prec) + "\n";
+    names->clear();
+    if (kind == kExprAdjoint) {
+        src += "static_assert(sizeof(ff::AdjArgs) == " + std::to_string(sizeof(AdjArgs)) + ", \"AdjArgs layout\");\n";
+        const bool small = P.dim <= 4;
+        names->push_back(std::string("&ff::k_adj<ffx::Sys, ") + R + ", " + K + (small ? ", 8, false>" : ", 1, true>"));
+        return src;
+    }
     src += "static_assert(sizeof(ff::RK4Args) == " + std::to_string(sizeof(RK4Args)) + ", \"RK4Args layout\");\n";
     src += "static_assert(sizeof(ff::ResetArgs) == " + std::to_string(sizeof(ResetArgs)) + ", \"ResetArgs layout\");\n";
     src += "static_assert(sizeof(ff::RecordArgs) == " + std::to_string(sizeof(RecordArgs)) + ", \"RecordArgs layout\");\n";
-    const std::string K = prec == FF_FP32_KAHAN ? "true" : "false";
     const std::string T = std::string("ffx::Sys, ") + R + ", " + K;
-    if (names) {
-        names->clear();
-        for (int ppt : {1, 2}) {
-            const std::string P2 = std::to_string(ppt);
-            names->push_back("&ff::k_rk4<" + T + ", " + P2 + ">");
-            names->push_back("&ff::k_rk4_reset<" + T + ", " + P2 + ">");
-            names->push_back("&ff::k_rk4_record<" + T + ", " + P2 + ", false>");
-            names->push_back("&ff::k_rk4_record<" + T + ", " + P2 + ", true>");
-        }
+    for (int ppt : {1, 2}) {
+        const std::string P2 = std::to_string(ppt);
+        names->push_back("&ff::k_rk4<" + T + ", " + P2 + ">");
+        names->push_back("&ff::k_rk4_reset<" + T + ", " + P2 + ">");
+        names->push_back("&ff::k_rk4_record<" + T + ", " + P2 + ", false>");
+        names->push_back("&ff::k_rk4_record<" + T + ", " + P2 + ", true>");
     }
     return src;
 }
 
 namespace {
 
-const char* const kHeaderNames[] = {"ff_kernel.h", "ff_math.h", "ff_rng.h"};
-const char* const kHeaders[] = {kEmbedded_ff_kernel_h, kEmbedded_ff_math_h, kEmbedded_ff_rng_h};
+const char* const kHeaderNames[] = {"ff_kernel.h", "ff_math.h", "ff_rng.h", "ff_adjoint_kernel.h"};
+const char* const kHeaders[] = {kEmbedded_ff_kernel_h, kEmbedded_ff_math_h, kEmbedded_ff_rng_h,
+                                kEmbedded_ff_adjoint_kernel_h};
+constexpr int kNumHeaders = 4;
 
-// Compiles the kernel source of `prec` for `arch`; code receives the code
-// object and lowered holds the mangled names of the kernels, in the order
-// of the name expressions.
-ff_status compile(const ExprProgram& P, int prec, const std::string& arch, std::vector<char>* code,
+// Compiles the program of `prec` and `kind` for `arch`; code receives the
+// code object and lowered holds the mangled names of the kernels, in the
+// order of the name expressions.
+ff_status compile(const ExprProgram& P, int prec, int kind, const std::string& arch, std::vector<char>* code,
                   std::vector<std::string>* lowered) {
     std::vector<std::string> names;
-    const std::string src = expr_source(P, prec, &names);
+    const std::string src = expr_program(P, prec, kind, &names);
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "ff_user_rhs.hip", 3, kHeaders, kHeaderNames) != HIPRTC_SUCCESS)
+    if (hiprtcCreateProgram(&prog, src.c_str(), "ff_user_rhs.hip", kNumHeaders, kHeaders, kHeaderNames) !=
+        HIPRTC_SUCCESS)
         return fail(FF_E_DEVICE, "hiprtcCreateProgram failed");
     for (const std::string& n : names) {
         if (hiprtcAddNameExpression(prog, n.c_str()) != HIPRTC_SUCCESS) {
@@ -449,12 +544,12 @@ ff_status compile(const ExprProgram& P, int prec, const std::string& arch, std::
 
 }  // namespace
 
-ff_status expr_prepare(const ff_system_s* sys, int prec) {
+ff_status expr_prepare(const ff_system_s* sys, int prec, int kind) {
     ExprProgram& P = *sys->expr;
     int dev = 0;
     if (hipError_t e = hipGetDevice(&dev)) return device_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(P.mu);
-    if (P.modules.count({dev, prec})) return FF_OK;
+    if (P.modules.count({dev, prec, kind})) return FF_OK;
     hipDeviceProp_t prop;
     if (hipError_t e = hipGetDeviceProperties(&prop, dev)) return device_fail(e, "hipGetDeviceProperties");
     std::vector<char> code;
@@ -463,16 +558,16 @@ ff_status expr_prepare(const ff_system_s* sys, int prec) {
     // code object built for "any" setting of a feature loads on every one
     std::string arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
-    if (ff_status s = compile(P, prec, arch, &code, &lowered)) return s;
+    if (ff_status s = compile(P, prec, kind, arch, &code, &lowered)) return s;
     ExprProgram::Module m;
     if (hipError_t e = hipModuleLoadData(&m.mod, code.data())) return device_fail(e, "hipModuleLoadData");
-    for (int k = 0; k < kExprKernels; ++k) {
+    for (size_t k = 0; k < lowered.size(); ++k) {
         if (hipError_t e = hipModuleGetFunction(&m.fn[k], m.mod, lowered[k].c_str())) {
             (void)hipModuleUnload(m.mod);
             return device_fail(e, "hipModuleGetFunction");
         }
     }
-    P.modules[{dev, prec}] = m;
+    P.modules[{dev, prec, kind}] = m;
     return FF_OK;
 }
 
@@ -483,7 +578,7 @@ hipError_t launch_rk4_expr(const ff_system_s* sys, const RK4Launch& L) {
     hipFunction_t fn[kExprKernels];
     {
         std::lock_guard<std::mutex> lk(P.mu);
-        auto it = P.modules.find({dev, L.prec});
+        auto it = P.modules.find({dev, L.prec, kExprForward});
         if (it == P.modules.end()) return hipErrorNotInitialized;  // expr_prepare was not called
         std::memcpy(fn, it->second.fn, sizeof fn);
     }
@@ -503,6 +598,24 @@ hipError_t launch_rk4_expr(const ff_system_s* sys, const RK4Launch& L) {
     const int which = L.record ? (L.reset ? 3 : 2) : (L.reset ? 1 : 0);
     return hipModuleLaunchKernel(fn[(ppt - 1) * 4 + which], (unsigned)grid, 1, 1, (unsigned)L.block, 1, 1, 0, L.stream,
                                  params, nullptr);
+}
+
+hipError_t launch_adj_expr(const ff_system_s* sys, const AdjLaunch& A) {
+    ExprProgram& P = *sys->expr;
+    int dev = 0;
+    if (hipError_t e = hipGetDevice(&dev)) return e;
+    hipFunction_t fn;
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.modules.find({dev, A.f.prec, kExprAdjoint});
+        if (it == P.modules.end()) return hipErrorNotInitialized;  // expr_prepare was not called
+        fn = it->second.fn[0];
+    }
+    const int64_t grid = (A.f.n + kAdjBlock - 1) / kAdjBlock;
+    if (grid <= 0) return hipSuccess;
+    AdjArgs a = make_adj_args(A);
+    void* params[1] = {&a};
+    return hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, kAdjBlock, 1, 1, 0, A.f.stream, params, nullptr);
 }
 
 void expr_destroy(ExprProgram* P) { delete P; }
@@ -563,10 +676,16 @@ ff_status ff_system_compile(ff_system_t sys, int32_t prec, const char* arch) {
     if (ff_status s = check_system(sys)) return s;
     if (!sys->expr) return fail(FF_E_INVALID, "not an expression system (built-in systems need no compilation)");
     if (prec != FF_FP64 && prec != FF_FP32 && prec != FF_FP32_KAHAN) return fail(FF_E_INVALID, "unknown precision");
-    if (!arch) return expr_prepare(sys, prec);
-    std::vector<char> code;
-    std::vector<std::string> lowered;
-    return compile(*sys->expr, prec, arch, &code, &lowered);
+    for (int kind : {kExprForward, kExprAdjoint}) {
+        if (!arch) {
+            if (ff_status s = expr_prepare(sys, prec, kind)) return s;
+        } else {
+            std::vector<char> code;
+            std::vector<std::string> lowered;
+            if (ff_status s = compile(*sys->expr, prec, kind, arch, &code, &lowered)) return s;
+        }
+    }
+    return FF_OK;
 }
 
 ff_status ff_system_source(ff_system_t sys, int32_t prec, char* buf, size_t cap, size_t* len) {
@@ -574,7 +693,7 @@ ff_status ff_system_source(ff_system_t sys, int32_t prec, char* buf, size_t cap,
     if (ff_status s = check_system(sys)) return s;
     if (!sys->expr) return fail(FF_E_INVALID, "not an expression system");
     if (prec != FF_FP64 && prec != FF_FP32 && prec != FF_FP32_KAHAN) return fail(FF_E_INVALID, "unknown precision");
-    const std::string src = expr_source(*sys->expr, prec, nullptr);
+    const std::string src = expr_struct(*sys->expr, prec);
     if (len) *len = src.size() + 1;
     if (buf && cap > 0) {
         const size_t n = src.size() < cap - 1 ? src.size() : cap - 1;

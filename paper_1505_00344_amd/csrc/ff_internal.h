@@ -53,8 +53,7 @@ struct AdjLaunch {
 };
 
 // Steps held in registers by the adjoint's innermost recompute (per system).
-int adj_tape_len(int rhs);
-constexpr int kAdjBlock = 256;
+int adj_tape_len(const ff_system_s* sys);
 
 // Per-system fused RK4 launchers (one translation unit each).
 hipError_t launch_rk4_linear(int dim, const RK4Launch& L);
@@ -100,10 +99,13 @@ RK4Launch make_launch(const ff_system_s* sys, const ff_batch* b, double dt, cons
                       hipStream_t stream);
 // Launch the fused RK4 kernel of the system for L.steps steps.
 hipError_t launch_rk4(const ff_system_s* sys, const RK4Launch& L);
-// Expression systems: compile and load the kernels of `prec` for the current
-// device unless that was done before (thread-safe).
-ff_status expr_prepare(const ff_system_s* sys, int prec);
+// Expression systems: compile and load the kernels of `prec` (the fused RK4
+// kernels, or the adjoint kernel) for the current device unless that was done
+// before (thread-safe).
+constexpr int kExprForward = 0, kExprAdjoint = 1;
+ff_status expr_prepare(const ff_system_s* sys, int prec, int kind);
 hipError_t launch_rk4_expr(const ff_system_s* sys, const RK4Launch& L);
+hipError_t launch_adj_expr(const ff_system_s* sys, const AdjLaunch& A);
 void expr_destroy(ExprProgram* p);
 // Default particles per thread / block for a system and precision.
 ff_tuning default_tuning(const ff_system_s* sys, int prec, int64_t nsteps);

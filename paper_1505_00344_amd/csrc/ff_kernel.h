@@ -35,6 +35,7 @@ namespace ff {
 constexpr int kMaxParams = 16;
 constexpr int kMaxPP = 4;  // per-particle parameter overrides (FF_MAX_PP)
 constexpr int kMaxDim = 15;
+constexpr int kAdjBlock = 256;  // threads per block of the adjoint kernel
 
 struct ParamBlock {
     double v[kMaxParams];

@@ -90,8 +90,11 @@ def test_source_shares_subtrees_and_hoists_parameter_terms(A):
     s = A.System.from_exprs(["exp(p0*p1) * x0 + exp(p0*p1)", "sin(x0)*sin(x0) - p1"], [0.5, 2.0])
     src = s.source("fp64")
     # exp(p0*p1) is state-free: computed once per particle in derive()
-    derive, f = src.split("void f(")
+    derive, rest = src.split("void f(")
+    f, vjp = rest.split("void vjp(")
     assert derive.count("exp(") == 1 and "exp(" not in f
+    # the vector-Jacobian product differentiates sin(x0)^2 through cos
+    assert "cos(" in vjp and "gx[0]" in vjp and "gp[0]" in vjp and "gp[1]" in vjp
     # sin(x0) appears twice in the text and once in the code
     assert f.count("sin(") == 1
     assert "sinf(" in s.source("fp32") and "sinf(" in s.source("fp32_kahan")
@@ -114,18 +117,21 @@ def test_compiles_for_gfx950_without_a_device(A, prec):
     q.compile(prec, arch="gfx950")
 
 
-def test_adjoint_and_groups_refuse_expression_systems(A):
+def test_groups_refuse_expression_systems_and_adjoint_layout(A):
     from paper_1505_00344_amd import _ffi
     L = _ffi.lib()
     s = A.System.from_exprs(LORENZ_EXPR, [10.0, 28.0, 8 / 3])
     b = _ffi.Batch()
     b.prec, b.state, b.n, b.ld = _ffi.FF_FP64, 4096, 10, 10
-    sz = ctypes.c_size_t()
-    assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz)) == _ffi.FF_E_UNSUPPORTED
-    assert L.ff_integrate_checkpointed(s.handle, ctypes.byref(b), 0.01, 100, 10, None, 0, None) == \
-        _ffi.FF_E_UNSUPPORTED
     g = A.make_groups([(s, b, 0.01)])
     assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == _ffi.FF_E_UNSUPPORTED
+    # the adjoint workspace of a small expression system is laid out like the
+    # built-in system of the same size (tape of eight steps)
+    builtin = A.System("lorenz", 3, [10.0, 28.0, 8 / 3])
+    sz, sz2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz)) == 0
+    assert L.ff_adjoint_workspace_size(builtin.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz2)) == 0
+    assert sz.value == sz2.value
 
 
 def test_noop_calls_compile_nothing(A):

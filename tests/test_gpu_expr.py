@@ -231,3 +231,128 @@ def test_fast_f32_flag(A, ora):
     err = mixed_error(got, ref)
     record("expr_rational_fast_fp32_kahan_vs_fp64", kahan=quantiles(err))
     assert np.quantile(err, 0.99) <= 1e-5 and err.max() <= 1e-4, quantiles(err)
+
+
+# --- the discrete adjoint of expression systems (vector-Jacobian products
+# generated by reverse-mode differentiation of the expressions) against the
+# oracle's forward-mode derivative of the same map ---
+
+def expr_adjoint(A, sysobj, x0, lamT, dt, nsteps, K, pp=None, pp_slot=(), dtype=torch.float64, kahan=False):
+    x = to_dev(x0, dtype)
+    ppt = None if pp is None else to_dev(pp, dtype)
+    comp = torch.zeros_like(x) if kahan else None
+    nb = A.adjoint_workspace_size(sysobj, x, nsteps, K, pparams=ppt, pp_slot=pp_slot, comp=comp)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda:0")
+    A.integrate_checkpointed(sysobj, x, dt, nsteps, K, ws, pparams=ppt, pp_slot=pp_slot, comp=comp)
+    lam = to_dev(lamT, dtype)
+    mu = None if ppt is None else torch.empty_like(ppt)
+    mug = torch.empty(max(sysobj.n_params, 1), dtype=torch.float64, device="cuda:0")
+    A.adjoint(sysobj, x, dt, nsteps, K, ws, lam, mu=mu, mu_global=mug, pparams=ppt, pp_slot=pp_slot,
+              prec="fp32_kahan" if kahan else None)
+    torch.cuda.synchronize()
+    return to_host(x), to_host(lam), (None if mu is None else to_host(mu)), to_host(mug)[:sysobj.n_params]
+
+
+def dual_reference(ora, exprs, params, x0, lamT, dt, nsteps, pp=None, pp_slot=()):
+    """dL/dx0, dL/dpp and dL/dp for L = sum lamT * x(T), from forward-mode runs."""
+    dim, n = x0.shape
+    lam0 = np.zeros_like(x0)
+    for d in range(dim):
+        dx0 = np.zeros_like(x0)
+        dx0[d] = 1.0
+        _, dxT = ora.expr_rk4_dual(exprs, params, x0, dt, nsteps, pp_slot=pp_slot, pparams=pp, dx0=dx0)
+        lam0[d] = (lamT * dxT).sum(axis=0)
+    mu = None
+    if pp is not None:
+        mu = np.zeros_like(pp)
+        for k in range(pp.shape[0]):
+            dpp = np.zeros_like(pp)
+            dpp[k] = 1.0
+            _, dxT = ora.expr_rk4_dual(exprs, params, x0, dt, nsteps, pp_slot=pp_slot, pparams=pp, dpp=dpp)
+            mu[k] = (lamT * dxT).sum(axis=0)
+    mug = np.zeros(len(params))
+    for q in range(len(params)):
+        if q in list(pp_slot):
+            # a slot overridden per particle: the sum of its per-particle gradients
+            mug[q] = mu[list(pp_slot).index(q)].sum()
+            continue
+        dp = np.zeros(len(params))
+        dp[q] = 1.0
+        _, dxT = ora.expr_rk4_dual(exprs, params, x0, dt, nsteps, pp_slot=pp_slot, pparams=pp, dparams=dp)
+        mug[q] = (lamT * dxT).sum()
+    return lam0, mu, mug
+
+
+def rel_err(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), tol.ADJ_FLOOR * max(np.abs(b).max(), 1e-300))
+
+
+ALL_FUNCS = ["1", "exp(x0) - x1", "pow(fabs(x1) + 1, p0) - 0.5 * x2",
+             "fmin(x0, x1) / (1 + fabs(x2)) - p1 * x3", "atan(x3) * tanh(x1) - sqrt(1 + x0*x0) * 0.1",
+             "log1p(x0*x0) + sinh(0.1 * x1) - cosh(0.1 * x2) + tan(0.3 * x4) - x5 + log(2 + cos(x3)) * sin(x4)"]
+
+
+@pytest.mark.parametrize("case", ["lorenz", "wc_backward", "all_functions"])
+def test_expression_adjoint_fp64_matches_oracle(A, ora, case):
+    rng = np.random.default_rng(13)
+    if case == "lorenz":
+        exprs, params, n = LORENZ_EXPR, I.LORENZ_PARAMS, 700
+        x0 = rng.uniform(-10, 10, (3, n))
+        x0[2] += 25
+        pp, slots, dt, nsteps, K = rng.uniform(20, 30, (1, n)), [1], 0.005, 150, 40
+    elif case == "wc_backward":
+        w = I.wilson_cowan_4m(n=600)
+        e = I.generate(w)
+        exprs, params, x0, pp, slots = WC_EXPR, w.params, e.state, e.pparams, w.pp_slot
+        dt, nsteps, K = -0.01, 120, 50
+    else:
+        exprs, params, n = ALL_FUNCS, [1.5, 0.3], 300
+        x0 = rng.uniform(-0.8, 0.8, (6, n))
+        pp, slots, dt, nsteps, K = rng.uniform(0.1, 0.5, (1, n)), [1], 0.01, 60, 25
+    s = A.System.from_exprs(exprs, params)
+    lamT = rng.normal(size=x0.shape)
+    xT, lam0, mu, mug = expr_adjoint(A, s, x0, lamT, dt, nsteps, K, pp=pp, pp_slot=slots)
+    assert np.array_equal(xT, ora.expr_rk4(exprs, params, x0, dt, nsteps, pp_slot=slots, pparams=pp)) or \
+        case != "lorenz"
+    ref_l, ref_mu, ref_g = dual_reference(ora, exprs, params, x0, lamT, dt, nsteps, pp=pp, pp_slot=slots)
+    for name, got, want in (("lambda0", lam0, ref_l), ("mu", mu, ref_mu), ("mu_global", mug, ref_g)):
+        e = rel_err(got, want)
+        record(f"expr_adjoint_fp64_{case}_{name}", err=quantiles(e.ravel()))
+        assert e.max() <= tol.ADJ_REL, (name, quantiles(e.ravel()))
+
+
+def test_expression_adjoint_equals_builtin_and_is_K_invariant(A, ora):
+    rng = np.random.default_rng(14)
+    n = 500
+    x0 = rng.uniform(-10, 10, (3, n))
+    x0[2] += 25
+    pp = rng.uniform(20, 30, (1, n))
+    lamT = rng.normal(size=x0.shape)
+    s = A.System.from_exprs(LORENZ_EXPR, I.LORENZ_PARAMS)
+    outs = [expr_adjoint(A, s, x0, lamT, 0.005, 120, K, pp=pp, pp_slot=[1]) for K in (120, 7, 50)]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    # the built-in Lorenz adjoint: same map, its own hand-written vector-Jacobian product
+    b = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    builtin = expr_adjoint(A, b, x0, lamT, 0.005, 120, 50, pp=pp, pp_slot=[1])
+    for got, want in zip(outs[0][1:], builtin[1:]):
+        assert rel_err(got, want).max() <= 1e-12
+
+
+def test_expression_adjoint_fp32_kahan_vs_fp64(A, ora):
+    rng = np.random.default_rng(15)
+    n = 2000
+    x0 = f32_inputs(rng.uniform(-10, 10, (3, n)) + np.array([[0.0], [0.0], [25.0]]))
+    pp = f32_inputs(rng.uniform(20, 30, (1, n)))
+    lamT = np.zeros((3, n))
+    lamT[2] = 1.0
+    s = A.System.from_exprs(LORENZ_EXPR, I.LORENZ_PARAMS)
+    dt32 = float(np.float32(0.005))
+    _, _, mu32, _ = expr_adjoint(A, s, x0.astype(np.float32), lamT.astype(np.float32), dt32, 200, 50,
+                                 pp=pp.astype(np.float32), pp_slot=[1], dtype=torch.float32, kahan=True)
+    _, dxT = ora.expr_rk4_dual(LORENZ_EXPR, I.LORENZ_PARAMS, x0, dt32, 200, pp_slot=[1], pparams=pp,
+                               dpp=np.ones_like(pp))
+    e = np.abs(mu32[0] - dxT[2]) / np.maximum(np.abs(dxT[2]), 1e-3 * max(1.0, np.abs(dxT[2]).max()))
+    record("expr_adjoint_fp32_kahan_lorenz", err=quantiles(e))
+    assert np.quantile(e, 0.99) <= tol.ADJ_FP32_P99, quantiles(e)
