@@ -163,9 +163,13 @@ ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n
  * ff_integrate_record compile the kernels of the batch's precision for the
  * current device on first use (hipRTC; about a second) and keep them with the
  * handle (ff_system_destroy waits for the device before unloading them).
- * The adjoint and the ragged-batch calls (ff_integrate_groups,
- * ff_autotune) hold compiled-in right-hand sides only and return
- * FF_E_UNSUPPORTED for such a system. */
+ * ff_integrate_checkpointed and ff_adjoint work as for the built-in systems:
+ * the vector-Jacobian product is generated by reverse-mode differentiation of
+ * the expressions (fabs has slope +1 at 0; fmin/fmax pass the adjoint to the
+ * argument they return, the first on a tie), and the adjoint kernel is
+ * compiled on the first ff_adjoint call of a precision.  The ragged-batch
+ * calls (ff_integrate_groups, ff_autotune) hold compiled-in right-hand sides
+ * only and return FF_E_UNSUPPORTED for such a system. */
 #define FF_EXPR_FAST_F32 1u
 ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n_params,
                                 const double* params, uint32_t flags, ff_system_t* out);
@@ -175,10 +179,12 @@ ff_status ff_system_create_expr(int32_t dim, const char* const* exprs, int32_t n
  * capturing a stream into a graph, since the first integration of a
  * precision otherwise compiles and loads during the call).  arch != NULL
  * (e.g. "gfx950"): compile only, with no device needed (a check that the
- * generated code builds).  FF_E_INVALID for a built-in system. */
+ * generated code builds).  Both the integration kernels and the adjoint
+ * kernel are compiled.  FF_E_INVALID for a built-in system. */
 ff_status ff_system_compile(ff_system_t sys, int32_t prec, const char* arch);
 
-/* The generated kernel source of an expression system for precision prec:
+/* The generated system (derived constants, right-hand side and its
+ * vector-Jacobian product) of an expression system for precision prec:
  * *len receives its size including the NUL; up to cap bytes are written to
  * buf (NUL-terminated; FF_E_NOMEM if cap is too small; buf may be NULL to
  * ask for the size). */

@@ -31,6 +31,30 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _check_out(t: torch.Tensor, name: str, shape, dtypes, min_numel: bool = False) -> None:
+    """A tensor the library writes: its dtype, contiguity and shape (or, with
+    min_numel, at least that many elements) must match what the call writes."""
+    if t.dtype not in dtypes or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {' or '.join(map(str, dtypes))} tensor")
+    if min_numel:
+        if t.numel() < shape:
+            raise ValueError(f"{name} needs at least {shape} elements")
+    elif tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+
+
+def _check_gpu(like: Optional[torch.Tensor], **tensors) -> None:
+    """Every tensor whose memory the library reads or writes must live on a GPU
+    (the one of the state, ``like``): a host pointer would reach a kernel."""
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a GPU tensor, not on {t.device}")
+        if like is not None and t.device != like.device:
+            raise ValueError(f"{name} is on {t.device} but the state is on {like.device}")
+
+
 class System:
     """An ODE system handle (ff_system_create)."""
 
@@ -95,6 +119,8 @@ def make_batch(state: torch.Tensor, n: Optional[int] = None, pparams: Optional[t
                prec: Optional[str] = None, offset: int = 0) -> Batch:
     """Describe a particle slice for the C ABI (no copies): particles
     ``offset .. offset + n - 1`` of the (dim, ld) arrays."""
+    _check_gpu(None, state=state)
+    _check_gpu(state, pparams=pparams, comp=comp)
     if state.dim() != 2:
         raise ValueError("state must have shape (dim, ld)")
     if not state.is_contiguous():
@@ -174,6 +200,7 @@ def make_reset(bounds, box, age: torch.Tensor, n_resets: torch.Tensor, n: int, m
     for name, t in (("age", age), ("n_resets", n_resets)):
         if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < offset + int(n):
             raise ValueError(f"{name} must be a contiguous int32 tensor covering the particles")
+    _check_gpu(None, age=age, n_resets=n_resets)
     r.age = age.data_ptr() + 4 * int(offset)
     r.n_resets = n_resets.data_ptr() + 4 * int(offset)
     return r
@@ -205,6 +232,7 @@ def integrate_record(sys: System, state: torch.Tensor, dt: float, nsteps: int, e
         out = torch.empty(shape, dtype=state.dtype, device=state.device)
     elif tuple(out.shape) != shape or out.dtype != state.dtype or not out.is_contiguous():
         raise ValueError(f"out must be a contiguous {state.dtype} tensor of shape {shape}")
+    _check_gpu(state, out=out)
     r = None if reset is None else make_reset(n=b.n, offset=offset, **reset)
     t = make_tuning(tuning)
     call("ff_integrate_record", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(every), int(stride),
@@ -231,6 +259,9 @@ def project_histogram(sys: System, state: torch.Tensor, axis_x: int, axis_y: int
         hist = torch.empty((ny, nx), dtype=torch.int32, device=dev)
     if n_dropped is None:
         n_dropped = torch.empty(1, dtype=torch.int64, device=dev)
+    _check_out(hist, "hist", (ny, nx), (torch.int32,))
+    _check_out(n_dropped, "n_dropped", 1, (torch.int64,), min_numel=True)
+    _check_gpu(state, hist=hist, n_dropped=n_dropped, workspace=workspace)
     ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel() * workspace.element_size())
     call("ff_project_histogram", sys.handle, ctypes.byref(b), int(axis_x), int(axis_y),
          float(x_range[0]), float(x_range[1]), float(y_range[0]), float(y_range[1]), int(nx), int(ny),
@@ -264,6 +295,9 @@ def render_image(sys: System, state: torch.Tensor, axis, mvp, width: int, height
         img = torch.empty((int(height), int(width), 3), dtype=torch.int32, device=state.device)
     if n_culled is None:
         n_culled = torch.empty(1, dtype=torch.int64, device=state.device)
+    _check_out(img, "img", (int(height), int(width), 3), (torch.int32,))
+    _check_out(n_culled, "n_culled", 1, (torch.int64,), min_numel=True)
+    _check_gpu(state, img=img, n_culled=n_culled)
     call("ff_render_image", sys.handle, ctypes.byref(b), ctypes.byref(r), img.data_ptr(), n_culled.data_ptr(),
          int(bool(accumulate)), _stream(stream))
     return img, n_culled
@@ -281,6 +315,7 @@ def integrate_checkpointed(sys: System, state: torch.Tensor, dt: float, nsteps: 
                            workspace: torch.Tensor, *, n=None, pparams=None, pp_slot=(), comp=None,
                            prec=None, stream=None) -> None:
     b = make_batch(state, n, pparams, pp_slot, comp, prec)
+    _check_gpu(state, workspace=workspace)
     call("ff_integrate_checkpointed", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(K),
          workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream))
 
@@ -291,6 +326,14 @@ def adjoint(sys: System, state: torch.Tensor, dt: float, nsteps: int, K: int, wo
             prec=None, stream=None) -> None:
     """ff_adjoint: ``lam`` holds dL/dx(T) on entry and dL/dx(0) on exit."""
     b = make_batch(state, n, pparams, pp_slot, comp, prec)
+    _check_out(lam, "lam", tuple(state.shape), (state.dtype,))
+    if mu is not None:
+        if pparams is None:
+            raise ValueError("mu is given but the batch has no per-particle parameters")
+        _check_out(mu, "mu", tuple(pparams.shape), (pparams.dtype,))
+    if mu_global is not None:
+        _check_out(mu_global, "mu_global", sys.n_params, (torch.float64,), min_numel=True)
+    _check_gpu(state, workspace=workspace, lam=lam, mu=mu, mu_global=mu_global)
     call("ff_adjoint", sys.handle, ctypes.byref(b), float(dt), int(nsteps), int(K), workspace.data_ptr(),
          workspace.numel() * workspace.element_size(), lam.data_ptr(), _ptr(mu), _ptr(mu_global),
          _stream(stream))
@@ -316,6 +359,7 @@ def groups_workspace_size(n_groups: int) -> int:
 def integrate_groups(groups, nsteps: int, *, tuning=None, workspace: Optional[torch.Tensor] = None,
                      stream=None) -> None:
     t = make_tuning(tuning)
+    _check_gpu(None, workspace=workspace)
     ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel() * workspace.element_size())
     call("ff_integrate_groups", groups, len(groups), int(nsteps),
          ctypes.byref(t) if t is not None else None, ws_ptr, ws_bytes, _stream(stream))

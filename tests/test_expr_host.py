@@ -145,16 +145,29 @@ def test_noop_calls_compile_nothing(A):
     assert L.ff_integrate(s.handle, ctypes.byref(b), 0.01, 0, None, None) == 0
 
 
-def test_make_reset_checks_tensor_sizes(A):
+def test_make_reset_checks_tensor_sizes_and_device(A):
     import torch
     age = torch.zeros(10, dtype=torch.int32)
     nres = torch.zeros(10, dtype=torch.int32)
     box = [(-1.0, 1.0)] * 3
-    r = A.make_reset(box, box, age, nres, 10)
-    assert r.age == age.data_ptr()
-    r = A.make_reset(box, box, age, nres, 4, offset=6)
-    assert r.age == age.data_ptr() + 24
-    with pytest.raises(ValueError):
+    with pytest.raises(ValueError, match="covering"):
         A.make_reset(box, box, age, nres, 5, offset=6)
-    with pytest.raises(ValueError):
+    with pytest.raises(ValueError, match="covering"):
         A.make_reset(box, box, age.to(torch.int64), nres, 10)
+    # right sizes, but host memory: refused before any pointer reaches a kernel
+    with pytest.raises(ValueError, match="GPU tensor"):
+        A.make_reset(box, box, age, nres, 10)
+
+
+def test_host_tensors_are_refused_before_any_call(A):
+    import torch
+    s = A.System("lorenz", 3, [10.0, 28.0, 8 / 3])
+    x = torch.zeros((3, 16), dtype=torch.float64)
+    for call in (lambda: A.integrate(s, x, 0.01, 10),
+                 lambda: A.project_histogram(s, x, 0, 1, (0.0, 1.0), (0.0, 1.0), 8, 8),
+                 lambda: A.render_image(s, x, (0, 1, 2), [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1]],
+                                        8, 8),
+                 lambda: A.integrate_record(s, x, 0.01, 10, 5),
+                 lambda: A.adjoint_workspace_size(s, x, 10, 5)):
+        with pytest.raises(ValueError, match="GPU tensor"):
+            call()

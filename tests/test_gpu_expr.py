@@ -356,3 +356,27 @@ def test_expression_adjoint_fp32_kahan_vs_fp64(A, ora):
     e = np.abs(mu32[0] - dxT[2]) / np.maximum(np.abs(dxT[2]), 1e-3 * max(1.0, np.abs(dxT[2]).max()))
     record("expr_adjoint_fp32_kahan_lorenz", err=quantiles(e))
     assert np.quantile(e, 0.99) <= tol.ADJ_FP32_P99, quantiles(e)
+
+
+def test_expression_system_in_a_captured_graph(A, ora):
+    # compiled ahead of capture (the first call of a precision would compile
+    # and load during the call); every replay matches the eager run, and four
+    # replays of 50 steps match the oracle's 200
+    w = I.lorenz_4096()
+    e = I.generate(w)
+    x = e.state[:, :e.counts[0]]
+    s = A.System.from_exprs(LORENZ_EXPR, w.params)
+    s.compile("fp64")
+    st_g = to_dev(x, torch.float64)
+    st_e = to_dev(x, torch.float64)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.integrate(s, st_g, 0.005, 50)
+    torch.cuda.synchronize()
+    assert torch.equal(st_g, st_e)  # capturing does not execute
+    for rep in range(4):
+        g.replay()
+        A.integrate(s, st_e, 0.005, 50)
+        torch.cuda.synchronize()
+        assert torch.equal(st_g, st_e), rep
+    assert np.array_equal(to_host(st_g), ora.expr_rk4(LORENZ_EXPR, w.params, x, 0.005, 200))
