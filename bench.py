@@ -377,7 +377,7 @@ def extended(A, I, torch, np):
                 "particle_steps_per_s_batched": ntot * nsteps / (batched * 1e-3),
                 "frame_ms_p50": float(np.percentile(frames, 50)), "frame_ms_p99": float(np.percentile(frames, 99))}
 
-    def next_rows():
+    def reset_record_render_expressions():
         """Reset rule, trajectory recording, render technique and expression
         right-hand sides on the paper's large ensembles."""
         r = {}
@@ -396,7 +396,7 @@ def extended(A, I, torch, np):
         st, comp = st0.clone(), torch.zeros_like(st0)
         plain = rate(lambda: A.integrate(builtin, st, 0.005, steps, pparams=pp, pp_slot=w.pp_slot, comp=comp))
         r["lorenz_8m_fp32_kahan_plain"] = plain
-        # N1: backward in time with the reset rule (escaping particles redrawn in the box)
+        # the reset rule, backward in time (escaping particles redrawn in the initial-condition box)
         bounds = [(-60.0, 60.0), (-80.0, 80.0), (-30.0, 100.0)]
         age = torch.zeros(n, dtype=torch.int32, device=dev)
         nres = torch.zeros(n, dtype=torch.int32, device=dev)
@@ -406,7 +406,7 @@ def extended(A, I, torch, np):
                                              comp=comp))
         res["resets_per_particle_step"] = float(nres.double().sum().item()) / (4 * n * steps)
         r["reset_lorenz_8m_backward_fp32_kahan"] = res
-        # N4: record every 10th step of every 16th particle
+        # trajectory recording: every 10th step of every 16th particle
         st, comp = st0.clone(), torch.zeros_like(st0)
         out = torch.empty((steps // 10, 3, (n + 15) // 16), dtype=torch.float32, device=dev)
         rec = rate(lambda: A.integrate_record(builtin, st, 0.005, steps, 10, 16, out=out, pparams=pp,
@@ -415,7 +415,7 @@ def extended(A, I, torch, np):
         rec["slowdown_vs_plain"] = rec["ms"] / plain["ms"]
         r["record_lorenz_8m_every10_stride16"] = rec
         del out
-        # N3: 8M particles drawn into a 1920 x 1080 frame, perspective camera
+        # the render technique: 8M particles drawn into a 1920 x 1080 frame, perspective camera
         f = 1.0 / np.tan(np.radians(60.0) / 2)
         aspect, near, far = 1920 / 1080, 1.0, 400.0
         proj = np.array([[f / aspect, 0, 0, 0], [0, f, 0, 0],
@@ -436,7 +436,7 @@ def extended(A, I, torch, np):
             r[f"render_8m_1080p_radius{radius}"] = {"ms": ms, "particles_per_s": n / (ms * 1e-3),
                                                     "culled": int(culled.item())}
         del img
-        # N2: the same systems given as expressions (compiled at run time)
+        # the same systems given as expressions (compiled at run time)
         lorenz_expr = A.System.from_exprs(["p0*(x1-x0)", "fma(x0, p1-x2, -x1)", "fma(x0, x1, -(p2*x2))"], w.params)
         t0 = time.perf_counter()
         lorenz_expr.compile("fp32_kahan")
@@ -504,7 +504,7 @@ def extended(A, I, torch, np):
         return r
 
     for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed),
-                     ("next_rows", next_rows)):
+                     ("reset_record_render_expressions", reset_record_render_expressions)):
         try:
             res[name] = fn()
         except Exception as ex:  # report and continue with the next workload
