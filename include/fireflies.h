@@ -257,8 +257,10 @@ ff_status ff_integrate_record(ff_system_t sys, const ff_batch* b, double dt_sign
  * n_dropped: device uint64 or NULL (not counted); accumulate == 0 first sets
  * hist (and *n_dropped) to zero.  workspace: device scratch of at least
  * ff_histogram_workspace_size() bytes, or NULL to use library-owned scratch
- * (allocated on first use on the device; pass your own under stream
- * capture). */
+ * (one buffer per device, allocated on first use and grown when needed: calls
+ * that use it concurrently on different streams of one device race, and
+ * under stream capture a workspace must be passed).  At most 2^31 - 1
+ * particles per call (FF_E_UNSUPPORTED beyond), grids up to 64M bins. */
 ff_status ff_histogram_workspace_size(int64_t n, int32_t nx, int32_t ny, size_t* bytes);
 ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
                                double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
@@ -328,8 +330,10 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
  * precision and signed step) advanced nsteps in one persistent launch per
  * steps_per_launch.  Every group must use FF_FP32 or FF_FP32_KAHAN or every
  * group FF_FP64.  Results are bitwise equal to ff_integrate on each group.
- * workspace: device scratch of at least ff_groups_workspace_size() bytes, or
- * NULL for library-owned scratch. */
+ * workspace: device scratch of at least ff_groups_workspace_size() bytes (it
+ * holds the tile counter of the launch), or NULL for a library-owned counter
+ * (one per device: launches that use it concurrently on different streams of
+ * one device race, and under stream capture a workspace must be passed). */
 typedef struct {
     ff_system_t sys;
     ff_batch b;
