@@ -182,7 +182,7 @@ def main():
             "traffic_unit": "bytes per launch (HBM read + write, calibrated rocprofv3 FETCH_SIZE/WRITE_SIZE)",
             "traffic_source": traffic_src,
             "algorithmic_bytes_per_launch": particles_per_launch * 36,
-            "kernel": "k_rk4<WilsonCowan<float>, Kahan>", "avg_launch_ms": round(avg_launch_ms, 4),
+            "kernel": "k_rk4<WilsonCowan<float>, float, Kahan, PPT 2>", "avg_launch_ms": round(avg_launch_ms, 4),
             "flop_per_particle_step": FLOP_PER_STEP["wilson_cowan"]["fp32_kahan"],
             "particles_per_launch": particles_per_launch, "steps_per_launch": w.nsteps}
     out = {

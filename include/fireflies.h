@@ -194,8 +194,8 @@ ff_status ff_system_source(ff_system_t sys, int32_t prec, char* buf, size_t cap,
  * dt_signed (Section 2.1; Appendix A.1-A.2).  In single precision the step is
  * rounded to float once, and h/2 and h/6 are formed in float.  dt_signed == 0
  * or nsteps == 0 (the paper's paused state) or n == 0 enqueue nothing.
- * tuning may be NULL (defaults: all steps in one launch, library-chosen
- * particles per thread and block size). */
+ * tuning may be NULL (defaults: up to 4096 steps per launch, particles per
+ * thread and block size chosen per system and precision from measurement). */
 ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int64_t nsteps,
                        const ff_tuning* tuning, void* stream);
 
