@@ -154,60 +154,102 @@ template <typename R> struct HHRate {
     R am, bm, ah, bh, an, bn, tv;
 };
 
+// k psi(u) with the fast single-precision functions, given den = (e^u - 1)/k
+// from the caller: for |u| < 1/2 the Bernoulli series of u/(e^u - 1),
+// 1 - u/2 + u^2/12 - u^4/720 + u^6/30240 (the next term, u^8/1209600, is below
+// 3.3e-9), with its coefficients scaled by k; otherwise u * rcp(den)
+// (cancellation in e^u - 1 costs at most a factor 2.6 there).  Both are
+// computed and one is selected.
 template <typename R>
-__device__ __forceinline__ R hh_psi(R u) {
-    if constexpr (M<R>::kFast) {
-        // |u| < 1/2: the Bernoulli series of u/(e^u - 1),
-        // 1 - u/2 + u^2/12 - u^4/720 + u^6/30240 (the next term, u^8/1209600,
-        // is below 3.3e-9); otherwise u * rcp(2^(u log2 e) - 1) with the
-        // hardware exp2 and rcp (cancellation in e^u - 1 costs at most a
-        // factor 2.6 there).  Both are computed and one is selected.
-        const R w = u * u;
-        const R series = M<R>::fma_(w, M<R>::fma_(w, M<R>::fma_(w, R(1.0 / 30240.0), R(-1.0 / 720.0)), R(1.0 / 12.0)),
-                                    M<R>::fma_(R(-0.5), u, R(1)));
-        const R direct = u * M<R>::rcp_(M<R>::exp2_(u * R(kLog2e)) - R(1));
-        return __builtin_fabsf(u) < R(0.5) ? series : direct;
-    } else {
-        const R q = M<R>::div_(u, M<R>::expm1_(u));
-        return (u == R(0)) ? R(1) : q;
-    }
+__device__ __forceinline__ R hh_psi_fast(R u, R den, double k) {
+    const R w = u * u;
+    const R series = M<R>::fma_(w, M<R>::fma_(w, M<R>::fma_(w, R(k / 30240.0), R(-k / 720.0)), R(k / 12.0)),
+                                M<R>::fma_(R(-0.5 * k), u, R(k)));
+    const R direct = u * M<R>::rcp_(den);
+    return __builtin_fabsf(u) < R(0.5) ? series : direct;
 }
 
 template <typename R>
-__device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg) {
+__device__ __forceinline__ R hh_psi(R u) {
+    const R q = M<R>::div_(u, M<R>::expm1_(u));
+    return (u == R(0)) ? R(1) : q;
+}
+
+// Rates of one neuron.  sgl = -sg * log2(e) (derived once per particle) is
+// used by the fast single-precision path only.
+template <typename R>
+__device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg, R sgl) {
     const R c10 = R(-1.0 / 10.0);
     const R v65 = V + R(65.0);
     HHRate<R> q;
-    q.am = hh_psi<R>((V + R(40.0)) * c10);
-    q.bm = R(4.0) * M<R>::expc(v65, -1.0 / 18.0);
-    q.ah = R(0.07) * M<R>::expc(v65, -1.0 / 20.0);
-    q.bh = M<R>::rcp_(R(1) + M<R>::expc(V + R(35.0), -1.0 / 10.0));
-    q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
-    q.bn = R(0.125) * M<R>::expc(v65, -1.0 / 80.0);
-    q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
+    if constexpr (M<R>::kFast) {
+        // One exponential serves three rates: with E = e^{-(V+40)/10},
+        // e^{-(V+35)/10} = E e^{1/2} and e^{-(V+55)/10} = E e^{-3/2}.  The
+        // constants are split into two floats (hi + lo, added by two fmas) so
+        // that their rounding does not bias the rates; the 1/10 of an scales
+        // psi's series and denominator, and the factors 4 and 1/8 of bm and bn
+        // are added to the base-2 exponent exactly.
+        constexpr double kE05 = 1.6487212707001281468, kE15x10 = 2.2313016014842982893;
+        const R um = (V + R(40.0)) * c10, un = (V + R(55.0)) * c10;
+        const R E = M<R>::exp2_(um * R(kLog2e));
+        q.am = hh_psi_fast<R>(um, E - R(1), 1.0);
+        q.an = hh_psi_fast<R>(
+            un, M<R>::fma_(E, R(kE15x10 - double(R(kE15x10))), M<R>::fma_(E, R(kE15x10), R(-10))), 0.1);
+        q.bh = M<R>::rcp_(M<R>::fma_(E, R(kE05 - double(R(kE05))), M<R>::fma_(E, R(kE05), R(1))));
+        q.bm = M<R>::exp2_(M<R>::fma_(v65, R(-kLog2e / 18.0), R(2)));
+        q.ah = R(0.07) * M<R>::exp2_(v65 * R(-kLog2e / 20.0));
+        q.bn = M<R>::exp2_(M<R>::fma_(v65, R(-kLog2e / 80.0), R(-3)));
+        q.tv = M<R>::rcp_(R(1) + M<R>::exp2_((V - th) * sgl));
+    } else {
+        q.am = hh_psi<R>((V + R(40.0)) * c10);
+        q.bm = R(4.0) * M<R>::expc(v65, -1.0 / 18.0);
+        q.ah = R(0.07) * M<R>::expc(v65, -1.0 / 20.0);
+        q.bh = M<R>::rcp_(R(1) + M<R>::expc(V + R(35.0), -1.0 / 10.0));
+        q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
+        q.bn = R(0.125) * M<R>::expc(v65, -1.0 / 80.0);
+        q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
+    }
     return q;
+}
+
+// dx/dt = a (1 - x) - b x of a gate; the fast path evaluates a - (a + b) x.
+template <typename R>
+__device__ __forceinline__ R hh_gate(R a, R b, R x) {
+    if constexpr (M<R>::kFast) return M<R>::fma_(-(a + b), x, a);
+    else return M<R>::fma_(a, R(1) - x, -(b * x));
 }
 
 template <typename R, int N> struct HHRing {
     static constexpr int D = 5 * N, NP = 14, NQ = 1, UNROLL = 1;
-    static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
-    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
+    static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
+        q[0] = M<R>::kFast ? -p[13] * R(kLog2e) : R(0);
+    }
+    static __device__ __forceinline__ void f(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D], R (&o)[D]) {
         const R invC = M<R>::rcp_(p[6]);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const R V = x[5 * j], m = x[5 * j + 1], h = x[5 * j + 2], n = x[5 * j + 3], s = x[5 * j + 4];
             const R spre = x[5 * ((j + N - 1) % N) + 4];
-            const HHRate<R> q = hh_rates<R>(V, p[12], p[13]);
-            const R IL = p[2] * (p[5] - V);
-            const R INa = ((p[0] * ((m * m) * m)) * h) * (p[3] - V);
+            const HHRate<R> q = hh_rates<R>(V, p[12], p[13], qd[0]);
+            const R gNa = (p[0] * ((m * m) * m)) * h;
             const R n2 = n * n;
-            const R IK = (p[1] * (n2 * n2)) * (p[4] - V);
-            const R Is = (p[8] * spre) * (p[9] - V);
-            o[5 * j] = ((((IL + INa) + IK) + Is) + p[7]) * invC;
-            o[5 * j + 1] = M<R>::fma_(q.am, R(1) - m, -(q.bm * m));
-            o[5 * j + 2] = M<R>::fma_(q.ah, R(1) - h, -(q.bh * h));
-            o[5 * j + 3] = M<R>::fma_(q.an, R(1) - n, -(q.bn * n));
-            o[5 * j + 4] = M<R>::fma_(p[10] * q.tv, R(1) - s, -(p[11] * s));
+            const R gK = p[1] * (n2 * n2);
+            const R gS = p[8] * spre;
+            if constexpr (M<R>::kFast) {
+                // the membrane currents accumulated by fma, Iext first
+                R I = M<R>::fma_(p[2], p[5] - V, p[7]);
+                I = M<R>::fma_(gNa, p[3] - V, I);
+                I = M<R>::fma_(gK, p[4] - V, I);
+                I = M<R>::fma_(gS, p[9] - V, I);
+                o[5 * j] = I * invC;
+            } else {
+                const R IL = p[2] * (p[5] - V);
+                o[5 * j] = ((((IL + gNa * (p[3] - V)) + gK * (p[4] - V)) + gS * (p[9] - V)) + p[7]) * invC;
+            }
+            o[5 * j + 1] = hh_gate(q.am, q.bm, m);
+            o[5 * j + 2] = hh_gate(q.ah, q.bh, h);
+            o[5 * j + 3] = hh_gate(q.an, q.bn, n);
+            o[5 * j + 4] = hh_gate(p[10] * q.tv, p[11], s);
         }
     }
     // psi'(u) = (expm1(u) - u e^u) / expm1(u)^2, psi'(0) = -1/2.
@@ -216,7 +258,7 @@ template <typename R, int N> struct HHRing {
         const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
         return (u == R(0)) ? R(-0.5) : d;
     }
-    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&)[NQ], const R (&x)[D],
+    static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R invC = M<R>::rcp_(p[6]);
         const R th = p[12], sg = p[13];
@@ -225,7 +267,7 @@ template <typename R, int N> struct HHRing {
             const int o = 5 * j, q5 = 5 * ((j + N - 1) % N);
             const R V = x[o], m = x[o + 1], h = x[o + 2], n = x[o + 3], s = x[o + 4];
             const R spre = x[q5 + 4];
-            const HHRate<R> q = hh_rates<R>(V, th, sg);
+            const HHRate<R> q = hh_rates<R>(V, th, sg, qd[0]);
             const R um = (V + R(40.0)) * R(-1.0 / 10.0), un = (V + R(55.0)) * R(-1.0 / 10.0);
             const R dam = dpsi(um) * R(-0.1);
             const R dbm = q.bm * R(-1.0 / 18.0);
