@@ -429,14 +429,17 @@ def extended(A, I, torch, np):
         img = torch.empty((1080, 1920, 3), dtype=torch.int32, device=dev)
         culled = torch.empty(1, dtype=torch.int64, device=dev)
         for radius in (0, 2):
+            rws = torch.empty(max(A.render_workspace_size(n, 1920, 1080, radius), 1), dtype=torch.uint8, device=dev)
+
             def draw():
                 A.render_image(builtin, st, (0, 1, 2), mvp, 1920, 1080, base=(0.2, 0.5, 1.0),
                                grad=[[0.01, 0, 0], [0, 0, 0], [0, 0, 0.01]], weight=0.05, radius=radius, img=img,
-                               n_culled=culled)
+                               n_culled=culled, workspace=rws)
             draw()
             ms = _time_stream(torch, draw, reps=5)
             r[f"render_8m_1080p_radius{radius}"] = {"ms": ms, "particles_per_s": n / (ms * 1e-3),
-                                                    "culled": int(culled.item())}
+                                                    "culled": int(culled.item()), "workspace_bytes": rws.numel()}
+            del rws
         del img
         # the same systems given as expressions (compiled at run time)
         lorenz_expr = A.System.from_exprs(["p0*(x1-x0)", "fma(x0, p1-x2, -x1)", "fma(x0, x1, -(p2*x2))"], w.params)

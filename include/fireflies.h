@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FF_ABI_VERSION 1
+#define FF_ABI_VERSION 2
 #define FF_MAX_PP 4 /* per-particle parameters per batch */
 
 typedef enum {
@@ -288,7 +288,13 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
  * and independent of particle order; a channel's sum wraps modulo 2^32 (after
  * 2^24 full-weight, full-colour hits of one pixel), so weight should keep the
  * densest pixel below that; n_culled: device uint64 or NULL; accumulate == 0
- * clears both first.  width * height <= 2^28, radius <= 64. */
+ * clears both first.  width * height <= 2^28, radius <= 64.
+ * workspace: device scratch of at least ff_render_workspace_size() bytes (0
+ * when the call needs none: sprites of radius > 8, images of more than 4096
+ * tiles of 64 x 32 pixels, or more than 2^29 particles), or NULL to use
+ * library-owned scratch (one buffer per device, allocated on first use and
+ * grown when needed: calls that use it concurrently on different streams of
+ * one device race, and under stream capture a workspace must be passed). */
 typedef struct {
     int32_t axis[3];
     double mvp[16];
@@ -300,8 +306,10 @@ typedef struct {
     int32_t radius;
 } ff_render;
 
+ff_status ff_render_workspace_size(int64_t n, const ff_render* r, size_t* bytes);
 ff_status ff_render_image(ff_system_t sys, const ff_batch* b, const ff_render* r, uint32_t* img,
-                          uint64_t* n_culled, int32_t accumulate, void* stream);
+                          uint64_t* n_culled, int32_t accumulate, void* workspace,
+                          size_t workspace_bytes, void* stream);
 
 /* Discrete adjoint (exact gradient of the RK4 map above with respect to the
  * initial state and the parameters; the Kahan update is differentiated as

@@ -18,7 +18,7 @@ FF_RHS_LINEAR, FF_RHS_LORENZ, FF_RHS_WILSON_COWAN, FF_RHS_HH_RING = 0, 1, 2, 3
 FF_RHS_EXPR = 16
 FF_EXPR_FAST_F32 = 1
 FF_MAX_PP = 4
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -70,7 +70,8 @@ SIGNATURES = {
     "ff_integrate_reset": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _c.POINTER(Reset), _c.POINTER(Tuning), _vp]),
     "ff_integrate_record": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _i64, _i64, _vp, _c.POINTER(Reset),
                                    _c.POINTER(Tuning), _vp]),
-    "ff_render_image": (_i32, [_vp, _c.POINTER(Batch), _c.POINTER(Render), _vp, _vp, _i32, _vp]),
+    "ff_render_workspace_size": (_i32, [_i64, _c.POINTER(Render), _c.POINTER(_sz)]),
+    "ff_render_image": (_i32, [_vp, _c.POINTER(Batch), _c.POINTER(Render), _vp, _vp, _i32, _vp, _sz, _vp]),
     "ff_histogram_workspace_size": (_i32, [_i64, _i32, _i32, _c.POINTER(_sz)]),
     "ff_project_histogram": (_i32, [_vp, _c.POINTER(Batch), _i32, _i32, _dbl, _dbl, _dbl, _dbl,
                                     _i32, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),

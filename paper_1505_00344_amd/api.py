@@ -269,13 +269,7 @@ def project_histogram(sys: System, state: torch.Tensor, axis_x: int, axis_y: int
     return hist, n_dropped
 
 
-def render_image(sys: System, state: torch.Tensor, axis, mvp, width: int, height: int, *, base=(1.0, 1.0, 1.0),
-                 grad=None, origin=(0.0, 0.0, 0.0), weight: float = 1.0, radius: int = 0,
-                 img: Optional[torch.Tensor] = None, n_culled: Optional[torch.Tensor] = None,
-                 accumulate: bool = False, n=None, pparams=None, pp_slot=(), prec=None, stream=None, offset=0):
-    """ff_render_image: returns (img int32 view of uint32 [H, W, 3] with 8
-    fractional bits, n_culled)."""
-    b = make_batch(state, n, pparams, pp_slot, None, prec if prec != "fp32_kahan" else "fp32", offset)
+def _render_desc(axis, mvp, width, height, base, grad, origin, weight, radius):
     r = _ffi.Render()
     for i in range(3):
         r.axis[i] = int(axis[i])
@@ -291,15 +285,37 @@ def render_image(sys: System, state: torch.Tensor, axis, mvp, width: int, height
         r.grad[i] = g[i]
     r.weight = float(weight)
     r.radius = int(radius)
+    return r
+
+
+def render_workspace_size(n: int, width: int, height: int, radius: int = 0) -> int:
+    """ff_render_workspace_size: scratch bytes of a render of n particles."""
+    r = _render_desc((0, 0, 0), [0.0] * 16, width, height, (1.0, 1.0, 1.0), None, (0.0, 0.0, 0.0), 1.0, radius)
+    out = ctypes.c_size_t()
+    call("ff_render_workspace_size", int(n), ctypes.byref(r), ctypes.byref(out))
+    return out.value
+
+
+def render_image(sys: System, state: torch.Tensor, axis, mvp, width: int, height: int, *, base=(1.0, 1.0, 1.0),
+                 grad=None, origin=(0.0, 0.0, 0.0), weight: float = 1.0, radius: int = 0,
+                 img: Optional[torch.Tensor] = None, n_culled: Optional[torch.Tensor] = None,
+                 accumulate: bool = False, n=None, pparams=None, pp_slot=(), prec=None, stream=None, offset=0,
+                 workspace: Optional[torch.Tensor] = None):
+    """ff_render_image: returns (img int32 view of uint32 [H, W, 3] with 8
+    fractional bits, n_culled).  workspace: None (library-owned scratch) or a
+    device uint8 tensor of at least render_workspace_size() bytes."""
+    b = make_batch(state, n, pparams, pp_slot, None, prec if prec != "fp32_kahan" else "fp32", offset)
+    r = _render_desc(axis, mvp, width, height, base, grad, origin, weight, radius)
     if img is None:
         img = torch.empty((int(height), int(width), 3), dtype=torch.int32, device=state.device)
     if n_culled is None:
         n_culled = torch.empty(1, dtype=torch.int64, device=state.device)
     _check_out(img, "img", (int(height), int(width), 3), (torch.int32,))
     _check_out(n_culled, "n_culled", 1, (torch.int64,), min_numel=True)
-    _check_gpu(state, img=img, n_culled=n_culled)
+    _check_gpu(state, img=img, n_culled=n_culled, workspace=workspace)
+    ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel() * workspace.element_size())
     call("ff_render_image", sys.handle, ctypes.byref(b), ctypes.byref(r), img.data_ptr(), n_culled.data_ptr(),
-         int(bool(accumulate)), _stream(stream))
+         int(bool(accumulate)), ws_ptr, ws_bytes, _stream(stream))
     return img, n_culled
 
 

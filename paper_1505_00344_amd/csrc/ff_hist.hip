@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "ff_internal.h"
+#include "ff_scan.h"
 
 namespace ff {
 
@@ -123,78 +124,6 @@ __global__ void __launch_bounds__(kBlock) k_hist_count(const R* ax, const R* ay,
     add_drops(dropped, drops, &s_drop);
 }
 
-// Exclusive scan over a block of 1024 threads (16 wavefronts of 64):
-// returns the exclusive prefix of v and writes the block total to *total.
-__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t* wsum, uint32_t* total) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    if (wv == 0) {
-        uint32_t s = lane < 16 ? wsum[lane] : 0u;
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const uint32_t t = __shfl_up(s, off, 64);
-            if (lane >= off) s += t;
-        }
-        if (lane < 16) wsum[16 + lane] = s;  // inclusive scan of wave sums
-    }
-    __syncthreads();
-    const uint32_t before = wv ? wsum[16 + wv - 1] : 0u;
-    *total = wsum[16 + 15];
-    __syncthreads();
-    return before + inc - v;
-}
-
-// 2a. scan per tile (one block of 1024 threads per tile): counts[t][b] ->
-// exclusive prefix within tile t; tile_total[t] = kept particles of tile t.
-__global__ void __launch_bounds__(1024) k_hist_scan_tiles(uint32_t* counts, int nblk, uint32_t* tile_total) {
-    __shared__ uint32_t wsum[32];
-    uint32_t* row = counts + (int64_t)blockIdx.x * nblk;
-    uint32_t carry = 0;
-    for (int base = 0; base < nblk; base += 1024) {
-        const int b = base + threadIdx.x;
-        const uint32_t v = b < nblk ? row[b] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_scan_1024(v, wsum, &tot);
-        if (b < nblk) row[b] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) tile_total[blockIdx.x] = carry;
-}
-
-// 2b. scan over tiles (one block of 1024 threads): tile_start[t] = first
-// entry of tile t in `sorted` (tile_start[ntiles] = kept particles);
-// chunk_start[t] = first accumulate block of tile t.
-__global__ void __launch_bounds__(1024) k_hist_scan_top(const uint32_t* tile_total, int ntiles, uint32_t* tile_start,
-                                                        uint32_t* chunk_start) {
-    __shared__ uint32_t wsum[32];
-    uint32_t carry = 0, ccarry = 0;
-    for (int base = 0; base < ntiles; base += 1024) {
-        const int t = base + threadIdx.x;
-        const uint32_t v = t < ntiles ? tile_total[t] : 0u;
-        const uint32_t c = (uint32_t)((v + kAccChunk - 1) / kAccChunk);
-        uint32_t tot, ctot;
-        const uint32_t ex = block_scan_1024(v, wsum, &tot);
-        const uint32_t cex = block_scan_1024(c, wsum, &ctot);
-        if (t < ntiles) {
-            tile_start[t] = carry + ex;
-            chunk_start[t] = ccarry + cex;
-        }
-        carry += tot;
-        ccarry += ctot;
-    }
-    if (threadIdx.x == 0) {
-        tile_start[ntiles] = carry;
-        chunk_start[ntiles] = ccarry;
-    }
-}
-
 // 3. scatter
 __global__ void __launch_bounds__(kBlock) k_hist_scatter(const uint32_t* binbuf, int64_t n, int ntiles,
                                                          const uint32_t* offsets, const uint32_t* tile_start,
@@ -221,13 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_hist_accum(const uint16_t* sorted, i
     __shared__ uint32_t s[kTile];
     const uint32_t g = blockIdx.x;
     if (g >= chunk_start[ntiles]) return;  // uniform: more blocks than chunks were launched
-    int lo_t = 0, hi_t = ntiles;           // largest t with chunk_start[t] <= g
-    while (hi_t - lo_t > 1) {
-        const int mid = (lo_t + hi_t) >> 1;
-        if (chunk_start[mid] <= g) lo_t = mid;
-        else hi_t = mid;
-    }
-    const int t = lo_t;
+    const int t = tile_of_chunk(chunk_start, ntiles, g);
     const int64_t lo = (int64_t)tile_start[t] + (int64_t)(g - chunk_start[t]) * kAccChunk;
     const int64_t end = tile_start[t + 1];
     const int64_t hi = lo + kAccChunk < end ? lo + kAccChunk : end;
@@ -268,43 +191,6 @@ WsLayout layout(int64_t n, int64_t nbins) {
     return L;
 }
 
-// Library-owned scratch per device (grown on demand, kept for the process).
-struct Scratch {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-};
-std::mutex g_scratch_mu;
-std::vector<Scratch> g_scratch;
-
-ff_status get_scratch(size_t need, hipStream_t stream, void** out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
-    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
-    Scratch& s = g_scratch[dev];
-    if (s.bytes < need) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-            return fail(FF_E_NOMEM, "histogram scratch must be passed as `workspace` under stream capture");
-        if (s.ptr) {
-            e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return device_fail(e, "hipStreamSynchronize");
-            hipFree(s.ptr);
-            s.ptr = nullptr;
-            s.bytes = 0;
-        }
-        e = hipMalloc(&s.ptr, need);
-        if (e != hipSuccess) {
-            s.ptr = nullptr;
-            return fail(FF_E_NOMEM, std::string("hipMalloc of histogram scratch: ") + hipGetErrorString(e));
-        }
-        s.bytes = need;
-    }
-    *out = s.ptr;
-    return FF_OK;
-}
-
 template <typename R>
 hipError_t run_hist(const R* ax, const R* ay, int64_t n, const Geom& g, uint32_t* hist,
                     unsigned long long* dropped, bool accumulate, char* ws, hipStream_t st) {
@@ -334,9 +220,10 @@ hipError_t run_hist(const R* ax, const R* ay, int64_t n, const Geom& g, uint32_t
     hipLaunchKernelGGL((k_hist_count<R>), dim3(nblk), dim3(kBlock), 0, st, ax, ay, n, g, ntiles, binbuf, counts,
                        dropped);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_hist_scan_tiles, dim3(ntiles), dim3(1024), 0, st, counts, nblk, ttotal);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(ntiles), dim3(1024), 0, st, counts, nblk, ttotal);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_hist_scan_top, dim3(1), dim3(1024), 0, st, ttotal, ntiles, tstart, cstart);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ttotal, ntiles, (uint32_t)kAccChunk, tstart,
+                       cstart);
     if (hipError_t e = hipGetLastError()) return e;
     hipLaunchKernelGGL(k_hist_scatter, dim3(nblk), dim3(kBlock), 0, st, binbuf, n, ntiles, counts, tstart, sorted);
     if (hipError_t e = hipGetLastError()) return e;
@@ -347,6 +234,48 @@ hipError_t run_hist(const R* ax, const R* ay, int64_t n, const Geom& g, uint32_t
 }
 
 }  // namespace
+
+namespace {
+// Library-owned scratch per device and use (grown on demand, kept for the
+// process).
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::vector<Scratch> g_scratch[kScratchUses];
+}  // namespace
+
+ff_status library_scratch(int use, size_t need, hipStream_t stream, void** out) {
+    static const char* const kWhat[kScratchUses] = {"histogram", "render"};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    std::vector<Scratch>& per_dev = g_scratch[use];
+    if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1);
+    Scratch& s = per_dev[dev];
+    if (s.bytes < need) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return fail(FF_E_NOMEM, std::string(kWhat[use]) + " scratch must be passed as `workspace` under stream capture");
+        if (s.ptr) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return device_fail(e, "hipStreamSynchronize");
+            (void)hipFree(s.ptr);
+            s.ptr = nullptr;
+            s.bytes = 0;
+        }
+        e = hipMalloc(&s.ptr, need);
+        if (e != hipSuccess) {
+            s.ptr = nullptr;
+            return fail(FF_E_NOMEM, std::string("hipMalloc of ") + kWhat[use] + " scratch: " + hipGetErrorString(e));
+        }
+        s.bytes = need;
+    }
+    *out = s.ptr;
+    return FF_OK;
+}
 
 }  // namespace ff
 
@@ -401,7 +330,7 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
             ws = (char*)workspace;
         } else {
             void* p = nullptr;
-            if (ff_status s = get_scratch(need, st, &p)) return s;
+            if (ff_status s = library_scratch(kScratchHistogram, need, st, &p)) return s;
             ws = (char*)p;
         }
     }

@@ -75,6 +75,12 @@ void set_error(const std::string& msg);
 ff_status fail(ff_status code, const std::string& msg);
 ff_status device_fail(hipError_t e, const char* where);
 
+// Library-owned device scratch, one buffer per device and use, allocated on
+// first need and grown (after a sync of `stream`) when a call needs more;
+// refused under stream capture when it would have to grow.
+constexpr int kScratchHistogram = 0, kScratchRender = 1, kScratchUses = 2;
+ff_status library_scratch(int use, size_t need, hipStream_t stream, void** out);
+
 }  // namespace ff
 
 // The opaque system handle.

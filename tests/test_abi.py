@@ -36,7 +36,7 @@ def test_binding_covers_every_symbol():
 
 
 def test_abi_version(L):
-    assert L.ff_abi_version() == 1
+    assert L.ff_abi_version() == 2
 
 
 def test_system_create_validation(L):
@@ -165,3 +165,24 @@ def test_groups_validation(L):
     assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == _ffi.FF_E_INVALID
     g = A.make_groups([(s, _batch(), 0.0)])
     assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == 0  # nothing to do
+
+
+def test_render_workspace_size_selects_the_path(L):
+    from paper_1505_00344_amd import api as A
+    size = A.render_workspace_size
+    assert size(0, 1920, 1080, 2) == 0
+    assert size(1000, 1920, 1080, 2) > 0           # tiled: sprites of radius <= 8
+    assert size(1000, 1920, 1080, 8) > 0
+    assert size(1000, 1920, 1080, 9) == 0          # larger sprites: one thread per particle
+    assert size(1000, 3840, 2160, 1) > 0           # 4080 tiles of 64 x 32
+    assert size(1000, 4096, 2100, 1) == 0          # 4224 tiles
+    assert size(1 << 29, 64, 32, 0) > 0
+    assert size((1 << 29) + 1, 64, 32, 0) == 0     # uint32 entry offsets
+    # one entry per particle for points, up to four (2 x 2 tiles) for sprites
+    n = 1 << 20
+    assert size(n, 640, 480, 1) - size(n, 640, 480, 0) == 3 * 4 * n
+    for bad in ((1000, 0, 1080, 0), (1000, 1920, 1080, 65), (-1, 1920, 1080, 0)):
+        with pytest.raises(A._ffi.FirefliesError, match="FF_E_INVALID"):
+            size(*bad)
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_UNSUPPORTED"):
+        size(10, 1 << 15, 1 << 14, 0)              # more than 2^28 pixels

@@ -257,3 +257,39 @@ def test_more_than_2_31_particles(A, ora, kahan):
         A.project_histogram(s, st, 0, 2, (-20.0, 20.0), (0.0, 50.0), 64, 64)
     del st, comp
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("radius", [0, 2])
+def test_render_8m_1080p_matches_oracle(A, ora, radius):
+    # the render workload at full size: 8,388,608 particles, most of them in
+    # dense clusters (as an attractor projects onto few pixels) and the rest
+    # in a diffuse cloud, drawn on the host from a seeded generator, drawn at
+    # 1920 x 1080 through a perspective camera; the whole image and the culled
+    # count equal the oracle's
+    rng = np.random.default_rng(77)
+    n = 8 * 1024 * 1024
+    centres = np.array([[0.0, 0.0, 25.0], [8.0, 8.0, 27.0], [-8.0, -8.0, 27.0], [0.0, 0.0, 10.0], [0.0, 0.0, 40.0]])
+    spread = np.array([0.05, 0.5, 0.5, 3.0, 20.0])
+    k = rng.integers(0, len(centres), n)
+    pos = (centres[k] + rng.standard_normal((n, 3)) * spread[k, None]).T.astype(np.float32)
+    f = 1.0 / np.tan(np.radians(60.0) / 2)
+    aspect, near, far = 1920 / 1080, 1.0, 400.0
+    proj = np.array([[f / aspect, 0, 0, 0], [0, f, 0, 0],
+                     [0, 0, (far + near) / (near - far), 2 * far * near / (near - far)], [0, 0, -1, 0]])
+    view = np.eye(4)
+    view[:3, 3] = [0.0, -25.0, -120.0]
+    view[:3, :3] = [[1, 0, 0], [0, 0, 1], [0, -1, 0]]
+    mvp = proj @ view
+    kw = dict(base=(0.2, 0.5, 1.0), grad=[[0.01, 0, 0], [0, 0, 0], [0, 0, 0.01]], weight=0.05, radius=radius)
+    s = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    st = to_dev(pos, torch.float32)
+    assert A.render_workspace_size(n, 1920, 1080, radius) > 0  # the tiled path
+    img, cu = A.render_image(s, st, (0, 1, 2), mvp, 1920, 1080, **kw)
+    torch.cuda.synchronize()
+    got = to_host(img).view(np.uint32)
+    spec = ora.render_spec((0, 1, 2), mvp, 1920, 1080, **kw)
+    want, wc = ora.render(pos.astype(np.float64), spec)
+    assert int(cu.item()) == wc
+    assert np.array_equal(got, want)
+    assert want.max() > 1000 * 256 * 0.05 * 0.2  # hot pixels: many sprites on one pixel
+    del st, img

@@ -101,3 +101,88 @@ def test_accumulate_and_cull_nonfinite(A, ora):
     want, wc = ora.render(pos, spec)
     assert int(cu.item()) == 2 * wc == 6
     assert np.array_equal(to_host(img).view(np.uint32), 2 * want)
+
+
+def lorenz_positions(ora, n):
+    # positions on the Lorenz attractor from the oracle (n particles, 400 steps)
+    w = I.lorenz_4096(n=n)
+    e = I.generate(w)
+    return ora.rk4(ora.LORENZ, w.params, e.state, 0.005, 400)
+
+
+@pytest.mark.parametrize("radius,width,height,tiled", [
+    (0, 333, 277, True),      # ragged tiles on both axes
+    (3, 333, 277, True),
+    (8, 200, 100, True),      # the largest tiled sprite (19 pixels)
+    (9, 200, 100, False),     # larger sprites: one thread per particle
+    (1, 4096, 2100, False),   # more than 4096 tiles: one thread per particle
+    (2, 3840, 2160, True),    # 4K UHD: 4080 tiles
+])
+def test_tiled_and_direct_paths_match_oracle(A, ora, radius, width, height, tiled):
+    pos = lorenz_positions(ora, 6000)
+    assert (A.render_workspace_size(pos.shape[1], width, height, radius) > 0) == tiled
+    M = look_at_perspective([60.0, -50.0, 40.0], [0.0, 0.0, 25.0], [0.0, 0.0, 1.0], 45.0, width / height, 1.0,
+                            300.0)
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    got = check(A, ora, sysobj, pos, torch.float32,
+                dict(axis=[0, 1, 2], mvp=M, width=width, height=height, base=(0.2, 0.4, 0.9),
+                     grad=[[0.02, 0, 0], [0, 0.01, 0], [0, 0, -0.01]], origin=(0.0, 0.0, 25.0), weight=0.8,
+                     radius=radius))
+    assert got.sum() > 0
+
+
+def test_sprites_on_tile_borders_and_image_edges(A, ora):
+    # particles placed so that their sprites straddle tile borders (every 64th
+    # column, every 32nd row), the image corners and edges, and fall half off
+    # the image
+    W, H = 300, 170
+    xs = np.concatenate([np.arange(0, W + 1, 32) + d for d in (-0.5, 0.0, 0.25)])
+    ys = np.concatenate([np.arange(0, H + 1, 16) + d for d in (-0.25, 0.0, 0.5)])
+    px, py = np.meshgrid(xs, ys)
+    px, py = px.ravel(), py.ravel()
+    # orthographic: px = (x + 1) W / 2, py = (1 - y) H / 2
+    pos = np.stack([2 * px / W - 1, 1 - 2 * py / H, np.zeros_like(px)])
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    for radius in (0, 1, 4, 8):
+        check(A, ora, sysobj, pos, torch.float64,
+              dict(axis=[0, 1, 2], mvp=np.eye(4), width=W, height=H, base=(1.0, 0.5, 0.25), radius=radius))
+
+
+def test_explicit_workspace_and_too_small_workspace(A, ora):
+    pos = lorenz_positions(ora, 3000)
+    M = look_at_perspective([60.0, -50.0, 40.0], [0.0, 0.0, 25.0], [0.0, 0.0, 1.0], 45.0, 1.5, 1.0, 300.0)
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    st = to_dev(pos, torch.float64)
+    need = A.render_workspace_size(pos.shape[1], 300, 200, 2)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    img, cu = A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=2, workspace=ws)
+    spec = ora.render_spec([0, 1, 2], M, 300, 200, radius=2)
+    want, wc = ora.render(pos, spec)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(img).view(np.uint32), want) and int(cu.item()) == wc
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_NOMEM.*workspace too small"):
+        A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=2, workspace=ws[: need - 256])
+
+
+def test_render_in_captured_graph(A, ora):
+    # a captured render (with its workspace) replayed several times, with eager
+    # work in between, equals the eager render every time
+    pos = lorenz_positions(ora, 5000)
+    M = look_at_perspective([60.0, -50.0, 40.0], [0.0, 0.0, 25.0], [0.0, 0.0, 1.0], 45.0, 1.5, 1.0, 300.0)
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    st = to_dev(pos, torch.float32)
+    ws = torch.empty(A.render_workspace_size(pos.shape[1], 300, 200, 1), dtype=torch.uint8, device="cuda:0")
+    img = torch.empty((200, 300, 3), dtype=torch.int32, device="cuda:0")
+    cu = torch.empty(1, dtype=torch.int64, device="cuda:0")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=1, img=img, n_culled=cu, workspace=ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        e_img, e_cu = A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=1)
+        torch.cuda.synchronize()
+        assert torch.equal(img, e_img) and int(cu.item()) == int(e_cu.item()), rep
+        # eager work between replays: the next replay sees the moved particles
+        A.integrate(sysobj, st, 0.005, 5)
+        torch.cuda.synchronize()
