@@ -17,15 +17,34 @@ template <> struct M<double> {
     // exp(x * c) for a compile-time constant c: the product is rounded, then exp
     static __device__ __forceinline__ double expc(double x, double c) { return exp(x * c); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
-    static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
+    // 1/x: the hardware estimate (v_rcp_f64) refined by two Newton steps,
+    // within 1 ulp (not always the correctly rounded quotient, which costs
+    // about twice the instructions); for zero, subnormal and infinite x the
+    // estimate itself is returned, which is IEEE's 1/x there (+-inf, +-0).
+    static constexpr int kZeroSubInf = (1 << 2) | (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7) | (1 << 9);
+    static __device__ __forceinline__ double rcp_(double x) {
+        const double r0 = __builtin_amdgcn_rcp(x);
+        double r = __builtin_fma(__builtin_fma(-x, r0, 1.0), r0, r0);
+        r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+        return __builtin_amdgcn_class(x, kZeroSubInf) ? r0 : r;
+    }
+    // a/b: a times that reciprocal with one residual correction (within
+    // 1 ulp); the same special cases fall back to a * estimate.
+    static __device__ __forceinline__ double div_(double a, double b) {
+        const double r0 = __builtin_amdgcn_rcp(b);
+        double r = __builtin_fma(__builtin_fma(-b, r0, 1.0), r0, r0);
+        r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+        const double q = a * r;
+        const double qc = __builtin_fma(__builtin_fma(-b, q, a), r, q);
+        return __builtin_amdgcn_class(b, kZeroSubInf) ? a * r0 : qc;
+    }
 };
 // Single precision.  By default (FF_FAST_F32 = 1) the exponential is the
 // hardware 2^x (v_exp_f32) with log2(e) folded into the argument's scale, and
 // reciprocals/divisions use v_rcp_f32 (each about 1 ulp); expm1 stays the
 // library function because psi(u) near u = 0 needs it.  FF_FAST_F32 = 0 uses
 // the library expf and correctly rounded division instead.  Double precision
-// always uses the library exp/expm1 and correctly rounded division.
+// uses the library exp/expm1 and a Newton-refined reciprocal (below).
 #ifndef FF_FAST_F32
 #define FF_FAST_F32 1
 #endif
