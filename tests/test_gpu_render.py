@@ -186,3 +186,22 @@ def test_render_in_captured_graph(A, ora):
         # eager work between replays: the next replay sees the moved particles
         A.integrate(sysobj, st, 0.005, 5)
         torch.cuda.synchronize()
+
+
+def test_empty_batch_and_offset_slice(A, ora):
+    # n = 0 clears the image and the culled count and draws nothing; a slice
+    # (offset, n) of a larger ensemble draws exactly those particles
+    pos = lorenz_positions(ora, 5000)
+    M = look_at_perspective([60.0, -50.0, 40.0], [0.0, 0.0, 25.0], [0.0, 0.0, 1.0], 45.0, 1.5, 1.0, 300.0)
+    sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    st = to_dev(pos, torch.float32)
+    img = torch.full((200, 300, 3), 7, dtype=torch.int32, device="cuda:0")
+    cu = torch.full((1,), 7, dtype=torch.int64, device="cuda:0")
+    A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=2, img=img, n_culled=cu, n=0)
+    torch.cuda.synchronize()
+    assert int(img.abs().sum().item()) == 0 and int(cu.item()) == 0
+    img, cu = A.render_image(sysobj, st, [0, 1, 2], M, 300, 200, radius=2, offset=1234, n=2345)
+    torch.cuda.synchronize()
+    sub = np.asarray(pos[:, 1234:1234 + 2345], dtype=np.float32).astype(np.float64)
+    want, wc = ora.render(sub, ora.render_spec([0, 1, 2], M, 300, 200, radius=2))
+    assert np.array_equal(to_host(img).view(np.uint32), want) and int(cu.item()) == wc
