@@ -293,3 +293,28 @@ def test_render_8m_1080p_matches_oracle(A, ora, radius):
     assert np.array_equal(got, want)
     assert want.max() > 1000 * 256 * 0.05 * 0.2  # hot pixels: many sprites on one pixel
     del st, img
+
+
+def test_render_beyond_the_tiled_limit_is_additive(A):
+    # 2^29 + 4096 particles exceed the tiled route's limit, so one call takes
+    # the direct route; drawing the first 2^29 (tiled) and accumulating the
+    # remaining 4096 (tiled) must give the same image and culled count bit for
+    # bit (integer sums; both routes evaluate the same per-pixel formula).
+    # Positions: a seeded device generator, uniform in a box slightly larger
+    # than the view volume, so some particles are culled.
+    n = (1 << 29) + 4096
+    g = torch.Generator(device="cuda:0").manual_seed(1505)
+    st = torch.rand((3, n), generator=g, device="cuda:0", dtype=torch.float32).mul_(2.1).sub_(1.05)
+    s = A.System("lorenz", 3, I.LORENZ_PARAMS)
+    kw = dict(base=(1.0, 0.5, 0.25), grad=[[0.1, 0, 0], [0, 0.1, 0], [0, 0, 0.1]], weight=0.01, radius=1)
+    assert A.render_workspace_size(n, 640, 480, 1) == 0              # direct
+    assert A.render_workspace_size(1 << 29, 640, 480, 1) > 0         # tiled
+    img, cu = A.render_image(s, st, (0, 1, 2), np.eye(4), 640, 480, **kw)
+    img2, cu2 = A.render_image(s, st, (0, 1, 2), np.eye(4), 640, 480, n=1 << 29, **kw)
+    A.render_image(s, st, (0, 1, 2), np.eye(4), 640, 480, offset=1 << 29, n=4096, img=img2, n_culled=cu2,
+                   accumulate=True, **kw)
+    torch.cuda.synchronize()
+    assert int(cu.item()) == int(cu2.item()) > 0
+    assert torch.equal(img, img2) and bool((img != 0).any())
+    del st, img, img2
+    torch.cuda.empty_cache()
