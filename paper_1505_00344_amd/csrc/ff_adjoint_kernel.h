@@ -136,8 +136,14 @@ __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ
     for (int d = 0; d < D; ++d) lam[d] = lam[d] + gs[d];
 }
 
+// Blocks of kAdjBlock threads that the adjoint kernel of system S must fit
+// on one CU, i.e. a register cap (1: none); specialised where measured.
+template <class S> struct AdjMinBlocks {
+    static constexpr int value = 1;
+};
+
 template <class S, typename R, bool KAHAN, int T, bool LOWREG>
-__global__ void __launch_bounds__(kAdjBlock) k_adj(AdjArgs a) {
+__global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjArgs a) {
     constexpr int D = S::D, NP = S::NP;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = i0 < a.n;

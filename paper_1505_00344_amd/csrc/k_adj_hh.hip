@@ -9,6 +9,14 @@ namespace ff {
 template <typename R> using HH1 = HHRing<R, 1>;
 template <typename R> using HH3 = HHRing<R, 3>;
 
+// The compensated single-precision three-neuron step takes 268 VGPRs, one
+// wave per SIMD; capped at 256 (two waves, 12 registers spilled) its reverse
+// sweep of 1M particles x 2000 steps took 313 instead of 360 ms.  Double
+// precision would spill 184 registers (1198 instead of 960 ms): no cap.
+template <int N> struct AdjMinBlocks<HHRing<float, N>> {
+    static constexpr int value = 2;
+};
+
 hipError_t launch_adj_hh(int neurons, const AdjLaunch& A) {
     switch (neurons) {
         case 1: return dispatch_adj<HH1, 1, true>(A);
