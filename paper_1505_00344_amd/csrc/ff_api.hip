@@ -1,4 +1,5 @@
 // ff_api.hip — C ABI: system handles, validation, errors, and ff_integrate.
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -238,6 +239,21 @@ ff_status ff_integrate(ff_system_t sys, const ff_batch* b, double dt_signed, int
 
 namespace ff {
 namespace {
+// The smallest float >= b and the largest float <= b (b not NaN): a float
+// state compared with them decides exactly as the double comparison would.
+float float_at_or_above(double b) {
+    if (b > FLT_MAX) return INFINITY;
+    if (b < -FLT_MAX) return std::isinf(b) ? -INFINITY : -FLT_MAX;
+    const float f = (float)b;  // nearest; in range here
+    return (double)f < b ? std::nextafter(f, INFINITY) : f;
+}
+float float_at_or_below(double b) {
+    if (b < -FLT_MAX) return -INFINITY;
+    if (b > FLT_MAX) return std::isinf(b) ? INFINITY : FLT_MAX;
+    const float f = (float)b;
+    return (double)f > b ? std::nextafter(f, -INFINITY) : f;
+}
+
 ff_status fill_reset(const ff_system_s* sys, const ff_batch* b, const ff_reset* reset, ResetArgs* r) {
     if (!reset->bound_lo || !reset->bound_hi || !reset->box_lo || !reset->box_hi)
         return fail(FF_E_INVALID, "reset bounds and box must be given");
@@ -253,6 +269,8 @@ ff_status fill_reset(const ff_system_s* sys, const ff_batch* b, const ff_reset* 
     for (int d = 0; d < sys->dim; ++d) {
         r->blo[d] = reset->bound_lo[d];
         r->bhi[d] = reset->bound_hi[d];
+        r->blf[d] = float_at_or_above(r->blo[d]);
+        r->bhf[d] = float_at_or_below(r->bhi[d]);
         r->wd[d] = reset->box_hi[d] - reset->box_lo[d];
         r->lod[d] = reset->box_lo[d];
         r->wf[d] = (float)r->wd[d];

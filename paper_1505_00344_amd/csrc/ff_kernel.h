@@ -101,6 +101,7 @@ struct RK4Args {
 // FP32: u = (a >> 8) * 2^-24 from word d; x = fma(width, u, lo).
 struct ResetArgs {
     double blo[kMaxDim], bhi[kMaxDim];  // bounds, compared in double
+    float blf[kMaxDim], bhf[kMaxDim];   // smallest float >= blo, largest float <= bhi
     double wd[kMaxDim], lod[kMaxDim];   // box width and low end (double)
     float wf[kMaxDim], lof[kMaxDim];    // the same rounded to float
     int64_t max_age;
@@ -117,13 +118,19 @@ struct RecordArgs {
     int64_t every, stride, m, step0;  // step0: global index of this launch's first step
 };
 
+// Lanes of a wave that must need a redraw before the wave draws for them.
+constexpr int kRefillLanes = 8;
+
+// For a float v, v >= blo exactly when v >= blf (and likewise above), so
+// single-precision states are tested against the float thresholds without a
+// conversion to double.
 template <typename R, int D>
 __device__ __forceinline__ bool escaped(const R (&x)[D], const ResetArgs& r) {
     bool out = false;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const double v = (double)x[d];
-        out = out || !(v >= r.blo[d] && v <= r.bhi[d]);
+        if constexpr (sizeof(R) == sizeof(float)) out = out || !(x[d] >= r.blf[d] && x[d] <= r.bhf[d]);
+        else out = out || !(x[d] >= r.blo[d] && x[d] <= r.bhi[d]);
     }
     return out;
 }
@@ -207,16 +214,29 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
     const R h = R(a.h), h2 = R(a.h2), h6 = R(a.h6);
     int32_t age[PPT];
     uint32_t nres[PPT];
+    // A redraw depends only on (particle, reset count), so each particle's
+    // next one is drawn ahead: nxt[j] holds draw number nres[j] while
+    // fresh[j].  Drawing inside the reset branch would run Philox's ten
+    // multiply rounds for most waves at most steps (a few lanes of a wave
+    // reset in most steps); instead a reset takes nxt[j] and a wave refills
+    // its consumed draws together once kRefillLanes lanes need one.  The
+    // values are the same draws, so results do not change.
+    R nxt[PPT][RESET ? D : 1];
+    bool fresh[PPT];
     if constexpr (RESET) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             age[j] = rs->age[idx[j]];
             nres[j] = rs->nres[idx[j]];
+            redraw<D>(nxt[j], *rs, rs->id_offset + (uint64_t)idx[j], nres[j]);
+            fresh[j] = true;
         }
     }
     // steps per loop trip: each system's own measured choice (two lets the
-    // loop-carried state of Lorenz avoid register copies)
-#pragma unroll S::UNROLL
+    // loop-carried state of Lorenz avoid register copies); one with the reset
+    // rule, whose wave-wide refill vote cannot be unrolled
+    constexpr int kStepsPerTrip = RESET ? 1 : S::UNROLL;
+#pragma unroll kStepsPerTrip
     for (int64_t s = 0; s < a.steps; ++s) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -224,11 +244,30 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
             if constexpr (RESET) {
                 age[j] += 1;
                 if (escaped<R, D>(x[j], *rs) || (rs->max_age >= 0 && age[j] > rs->max_age)) {
-                    redraw<D>(x[j], *rs, rs->id_offset + (uint64_t)idx[j], nres[j]);
+                    // a second reset before the refill draws here
+                    if (!fresh[j]) redraw<D>(nxt[j], *rs, rs->id_offset + (uint64_t)idx[j], nres[j]);
 #pragma unroll
-                    for (int d = 0; d < D; ++d) c[j][d] = R(0);
+                    for (int d = 0; d < D; ++d) {
+                        x[j][d] = nxt[j][d];
+                        c[j][d] = R(0);
+                    }
                     age[j] = 0;
                     nres[j] += 1;
+                    fresh[j] = false;
+                }
+            }
+        }
+        if constexpr (RESET) {
+            bool need = false;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) need = need || !fresh[j];
+            if (__popcll(__ballot(need)) >= kRefillLanes) {  // uniform over the wave
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (!fresh[j]) {
+                        redraw<D>(nxt[j], *rs, rs->id_offset + (uint64_t)idx[j], nres[j]);
+                        fresh[j] = true;
+                    }
                 }
             }
         }

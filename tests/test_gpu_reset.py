@@ -59,6 +59,46 @@ def test_lorenz_4096_with_resets_matches_oracle_bitwise(A, ora, prec):
     assert np.all(np.isfinite(outs[1][0]))
 
 
+BOUND_CASES = [(60.000001, 80.5), (-1e-30, 1e-30), (-np.inf, 3.0), (-1e300, 1e300), (1.5, 1.5), (-np.inf, np.inf)]
+
+
+def float_neighbours(b):
+    f = np.float32(np.clip(b, -np.finfo(np.float32).max, np.finfo(np.float32).max))
+    out = [f]
+    with np.errstate(over="ignore"):  # stepping past the largest float gives inf
+        for _ in range(2):
+            out.append(np.nextafter(out[-1], np.float32(np.inf)))
+        g = f
+        for _ in range(2):
+            g = np.nextafter(g, np.float32(-np.inf))
+            out.append(g)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_kahan", "fp64"])
+def test_bounds_between_floats_decide_like_double(A, ora, prec):
+    # x' = 0 x keeps a finite state exactly, so the bounds test sees the
+    # initial values: bounds between two floats, at a float, infinite and
+    # beyond the float range, with particles on the floats around each bound;
+    # the single-precision kernels test against float thresholds, which must
+    # decide exactly as the double comparison of the rule does
+    vals = {np.float32(v) for v in (0.0, 1.0, -1.0, np.inf, -np.inf)}
+    for lo, hi in BOUND_CASES:
+        for b in (lo, hi):
+            vals.update(float_neighbours(b))
+    fin = np.array(sorted(v for v in vals if np.isfinite(v)), dtype=np.float32)
+    x = np.concatenate([fin, np.array([np.inf, -np.inf, np.nan], dtype=np.float32)])[None, :]
+    x = x.astype(np.float64) if prec == "fp64" else x
+    for lo, hi in BOUND_CASES:
+        got = gpu_reset(A, "linear", 1, [0.0], x, 0.01, 1, [(lo, hi)], [(0.25, 0.75)], seed=7, prec=prec)
+        ref = ora.rk4_reset(ora.LINEAR, [0.0], x, 0.01, 1, [(lo, hi)], [(0.25, 0.75)], seed=7, prec=prec)
+        assert np.array_equal(got[0], ref[0], equal_nan=True), (lo, hi)
+        assert np.array_equal(got[3], ref[3]), (lo, hi)
+        # the finite particles are reset exactly where the double comparison fails
+        xf = x[0, :len(fin)].astype(np.float64)
+        assert np.array_equal(got[3][:len(fin)] == 1, ~((xf >= lo) & (xf <= hi))), (lo, hi)
+
+
 def test_wilson_cowan_backward_unit_square(A, ora):
     # the 2D model's setting of Section 2.1: ICs uniform on (0,1)^2, any
     # trajectory leaving the square is reset; backward particles leave it fast
