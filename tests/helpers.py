@@ -1,10 +1,20 @@
-"""Helpers shared by the GPU tests (no arithmetic of the method here)."""
+"""Helpers shared by the tests (no arithmetic of the method here)."""
 import json
 import os
 
 import numpy as np
 
 DEV = "cuda:0"
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """A fixture of printed or published values from tests/golden/ (JSON with
+    a `citation` field)."""
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
 
 
 def record(name, **values):

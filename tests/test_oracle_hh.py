@@ -12,6 +12,7 @@ firing (I ~ 6.25) pins the assembled single-neuron model.
 import numpy as np
 import pytest
 
+from helpers import golden
 from paper_1505_00344_amd.inputs import HH_PARAMS
 
 NAMES = ["gNa", "gK", "gL", "ENa", "EK", "EL", "C", "Iext", "gsyn", "Esyn", "rr", "rd", "th", "sg"]
@@ -60,12 +61,14 @@ def test_rates_match_1952_forms(ora, V):
 
 
 def test_resting_gates_and_potential(ora):
-    # gate steady states at rest (1952 convention v = 0): m = 0.0529,
-    # h = 0.5961, n = 0.3177 (Hodgkin & Huxley 1952)
+    # gate steady states at rest (1952 convention v = 0), printed to four
+    # decimals by Hodgkin & Huxley (1952)
+    g = golden("hh_resting_gates")
+    tol = 0.5 * 10.0 ** -g["printed_decimals"]
     am, bm, ah, bh, an, bn = oracle_rates(ora, -65.0)
-    assert abs(am / (am + bm) - 0.0529) < 5e-5
-    assert abs(ah / (ah + bh) - 0.5961) < 5e-5
-    assert abs(an / (an + bn) - 0.3177) < 5e-5
+    assert abs(am / (am + bm) - g["m"]) < tol
+    assert abs(ah / (ah + bh) - g["h"]) < tol
+    assert abs(an / (an + bn) - g["n"]) < tol
     # with no drive the neuron settles at rest near -65 mV
     x = np.array([[-70.0], [0.05], [0.6], [0.32], [0.0]])
     got = ora.rk4(ora.HH_RING, params(Iext=0.0, gsyn=0.0), x, 0.01, 20000)
@@ -92,10 +95,12 @@ def test_onset_of_repetitive_firing_near_6_25(ora):
     # Section 3: increasing I past ~6.25 gives a stable limit cycle (repetitive
     # firing).  Put neurons on the cycle with a strong drive, then lower it:
     # above the onset firing persists, below it the neuron falls silent.
+    onset = golden("hh_repetitive_firing_onset")["I_onset"]
     n = 4
     x = np.tile(np.array([[-65.0], [0.05], [0.6], [0.32], [0.0]]), (1, n))
     x, _ = run_traces(ora, x, np.full(n, 12.0), 10000)
-    I = np.array([5.0, 5.8, 6.8, 8.0])
+    I = np.array([5.0, 5.8, 6.8, 8.0])  # two below the printed onset, two above
+    assert I[1] < onset < I[2]
     x, v = run_traces(ora, x, I, 40000)
     last = v[-1000:]  # the last 100 ms
     spikes = [count_spikes(last[:, i]) for i in range(n)]

@@ -4,6 +4,7 @@ paper prints for its bifurcations."""
 import numpy as np
 import pytest
 
+from helpers import golden
 from paper_1505_00344_amd.inputs import LORENZ_BOX, random_state
 
 SIG, BETA = 10.0, 8.0 / 3.0
@@ -101,13 +102,16 @@ def test_pitchfork_at_r_equals_one(ora):
 
 @pytest.mark.parametrize("sign", [1, -1])
 def test_spirals_lose_stability_near_24_74(ora, sign):
-    # Section 2.2 prints that the two spirals stay stable until r ~ 24.74
+    # Section 2.2 prints the r up to which the two spirals stay stable
+    g = golden("lorenz_hopf")
+    r_printed, half = g["r_hopf"], 0.5 * 10.0 ** -g["printed_decimals"]
+
     def lam(r):
         c = c_plus(r) * np.array([sign, sign, 1.0])
         return np.linalg.eigvals(fd_jacobian(ora, P(r), c)).real.max()
-    assert lam(24.70) < 0 < lam(24.78)
+    assert lam(r_printed - 0.04) < 0 < lam(r_printed + 0.04)
     rH = SIG * (SIG + BETA + 3) / (SIG - BETA - 1)
-    assert abs(rH - 24.74) < 0.005
+    assert abs(rH - r_printed) < half
 
 
 def test_fourth_order_convergence_chaotic_short_horizon(ora):

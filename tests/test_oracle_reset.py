@@ -13,12 +13,11 @@ from scipy import stats
 
 from paper_1505_00344_amd.inputs import LORENZ_BOX, LORENZ_PARAMS, WC_BOX, WC_PARAMS
 
-KAT = [  # (counter, key, output) known-answer vectors of Philox4x32-10
-    ([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
-    ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
-    ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
-     [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]),
-]
+from helpers import golden
+
+# (counter, key, output) known-answer vectors of Philox4x32-10
+KAT = [([int(w, 16) for w in v["counter"]], [int(w, 16) for w in v["key"]], [int(w, 16) for w in v["output"]])
+       for v in golden("philox4x32_10_kat")["vectors"]]
 
 
 @pytest.mark.parametrize("ctr,key,want", KAT)
