@@ -7,7 +7,8 @@ import pytest
 from helpers import golden
 from paper_1505_00344_amd.inputs import LORENZ_BOX, random_state
 
-SIG, BETA = 10.0, 8.0 / 3.0
+G = golden("lorenz_regimes")
+SIG, BETA = G["sigma"], G["beta_numerator"] / G["beta_denominator"]
 
 
 def P(r):
@@ -77,8 +78,8 @@ def test_fixed_points_r28(ora):
 def test_r_below_one_all_particles_reach_origin(ora):
     # Section 2.2: for r < 1 the origin is the only stable fixed point and all
     # particles approach it (Fig. 3A box x in (-10,10), y in (-30,30), z in (0,50))
-    x = random_state(6, 3, 1000, [(-10, 10), (-30, 30), (0, 50)])
-    got = ora.rk4(ora.LORENZ, P(0.5), x, 0.005, 8000)
+    x = random_state(6, 3, 1000, [tuple(b) for b in G["origin_example_box"]])
+    got = ora.rk4(ora.LORENZ, P(G["r_origin_example"]), x, 0.005, 8000)
     assert np.linalg.norm(got, axis=0).max() < 1e-5
 
 
@@ -86,6 +87,7 @@ def test_r5_particles_reach_the_two_spirals(ora):
     # Section 2.2: at r = 5 the origin is a saddle and particles spiral into one
     # of two stable fixed points C+- = (+-sqrt(beta(r-1)), +-sqrt(beta(r-1)), r-1)
     x = random_state(7, 3, 2000, LORENZ_BOX)
+    assert G["r_spirals_example"] == 5.0
     got = ora.rk4(ora.LORENZ, P(5.0), x, 0.005, 8000)
     cp = c_plus(5.0)
     cm = cp * np.array([-1, -1, 1])
@@ -97,14 +99,36 @@ def test_r5_particles_reach_the_two_spirals(ora):
 def test_pitchfork_at_r_equals_one(ora):
     # Section 2.2: at r = 1 the origin loses stability (supercritical pitchfork)
     lam = lambda r: np.linalg.eigvals(fd_jacobian(ora, P(r), np.zeros(3))).real.max()
-    assert lam(0.95) < 0 < lam(1.05)
+    r1 = G["r_pitchfork"]
+    assert lam(r1 - 0.05) < 0 < lam(r1 + 0.05)
+
+
+def leave_origin(ora, r, h=0.001, T=30.0):
+    # start on the origin's unstable manifold (x > 0 side) and return x(T)
+    w, V = np.linalg.eig(np.array([[-SIG, SIG], [r, -1.0]]))
+    v = V[:, np.argmax(w)]
+    v = v / np.sign(v[0])
+    x0 = np.array([[1e-7 * v[0]], [1e-7 * v[1]], [0.0]])
+    return ora.rk4(ora.LORENZ, P(r), x0, h, int(round(T / h)))[:, 0]
+
+
+@pytest.mark.parametrize("h", [0.001, 0.0005])
+def test_homoclinic_crossover_near_13_926(ora, h):
+    # Section 2.2, Fig. 3C: below the homoclinic r a trajectory leaving the
+    # origin settles on the spiral of its own side, above it on the opposite
+    # one; the switch falls within the printed digits of r
+    rh, dec = G["r_homoclinic"], G["r_homoclinic_decimals"]
+    d = 2 * 10.0 ** -dec
+    below, above = leave_origin(ora, rh - d, h), leave_origin(ora, rh + d, h)
+    cb, ca = c_plus(rh - d), c_plus(rh + d)
+    assert np.linalg.norm(below - cb) < 1e-3 * np.linalg.norm(cb)
+    assert np.linalg.norm(above - ca * np.array([-1, -1, 1])) < 1e-3 * np.linalg.norm(ca)
 
 
 @pytest.mark.parametrize("sign", [1, -1])
 def test_spirals_lose_stability_near_24_74(ora, sign):
     # Section 2.2 prints the r up to which the two spirals stay stable
-    g = golden("lorenz_hopf")
-    r_printed, half = g["r_hopf"], 0.5 * 10.0 ** -g["printed_decimals"]
+    r_printed, half = G["r_hopf"], 0.5 * 10.0 ** -G["r_hopf_decimals"]
 
     def lam(r):
         c = c_plus(r) * np.array([sign, sign, 1.0])
