@@ -186,3 +186,13 @@ def test_render_workspace_size_selects_the_path(L):
             size(*bad)
     with pytest.raises(A._ffi.FirefliesError, match="FF_E_UNSUPPORTED"):
         size(10, 1 << 15, 1 << 14, 0)              # more than 2^28 pixels
+
+
+def test_histogram_grid_limit(L):
+    from paper_1505_00344_amd import api as A
+    assert A.histogram_workspace_size(1000, 8192, 8192) > 0             # 64M bins: the largest grid
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_UNSUPPORTED"):
+        A.histogram_workspace_size(1000, 8192, 8193)
+    assert A.histogram_workspace_size(1000, 128, 128) == 0              # one LDS histogram per block
+    with pytest.raises(A._ffi.FirefliesError, match="FF_E_INVALID"):
+        A.histogram_workspace_size(-1, 64, 64)

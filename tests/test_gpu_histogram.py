@@ -76,7 +76,8 @@ def test_wilson_cowan_full_size_parameter_axis(A, ora, dtype):
 
 
 @pytest.mark.parametrize("nx,ny,n", [(64, 64, 100003), (128, 128, 7), (1, 1, 5000), (16384, 1, 3000),
-                                     (700, 300, 250001), (4096, 4096, 60000)])
+                                     (700, 300, 250001), (4096, 4096, 60000),
+                                     (8192, 8192, 200001)])  # the largest grid: 64M bins, 4096 tiles
 def test_grid_shapes_and_ragged_sizes(A, ora, nx, ny, n):
     rng = np.random.default_rng(nx * 7 + ny)
     st = rng.normal(0, 0.6, size=(2, n))
