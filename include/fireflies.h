@@ -12,9 +12,12 @@
  * and Section 2.2); the current positions are projected onto two chosen axes
  * and accumulated additively on a pixel grid (Appendix A "Render Technique",
  * Appendix A.1 fragment shader with additive blending).  This library
- * computes exactly that, with unit weight per particle (a 2D count
- * histogram), plus the exact discrete adjoint of the RK4 map and a batched
- * launch over ragged groups of different systems.
+ * computes that: the RK4 advance in single precision (optionally with a
+ * compensated update) or double precision, the projection as an exact count
+ * histogram and as the paper's sprite image, the paper's reset rule, trajectory
+ * recording, right-hand sides given as expressions and compiled at run time,
+ * the exact discrete adjoint of the RK4 map, and a batched launch over ragged
+ * groups of different systems.
  *
  * Conventions for every function below.
  *   - Device memory: every array argument documented as "device" is memory
@@ -26,7 +29,11 @@
  *   - Element type follows ff_batch.prec: float for FF_FP32 and
  *     FF_FP32_KAHAN, double for FF_FP64.
  *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
- *     Calls only enqueue work; none synchronises the device.
+ *     Calls only enqueue work, with three exceptions stated where they
+ *     apply: ff_autotune times launches (it synchronises its stream), growing
+ *     library-owned scratch synchronises the stream before the old buffer is
+ *     freed, and ff_system_destroy of an expression system waits for the
+ *     device before unloading its kernels.
  *   - Errors: arguments are validated on the host before anything is
  *     enqueued; on failure nothing was enqueued and ff_last_error() explains
  *     why.  FF_E_DEVICE reports a HIP error (its text in ff_last_error()).
