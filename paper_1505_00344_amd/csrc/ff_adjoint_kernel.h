@@ -55,33 +55,32 @@ struct AdjArgs {
     int last;     // last segment processed (the first in time): write mu, mu_part
 };
 
-// Stage points of one step from x: y2 = x + (h/2)k1, y3 = x + (h/2)k2,
-// y4 = x + h k3 (stage s in 1..4; s = 1 returns x).
-template <class S, typename R>
-__device__ __forceinline__ void stage_point(const R (&p)[S::NP], const R (&q)[S::NQ], const R (&x)[S::D], int s,
-                                            R (&y)[S::D], R h, R h2) {
-    constexpr int D = S::D;
-    R k[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) y[d] = x[d];
-#pragma unroll 1
-    for (int j = 1; j < s; ++j) {
-        S::f(p, q, y, k);
-        const R w = (j == 3) ? h : h2;
-#pragma unroll
-        for (int d = 0; d < D; ++d) y[d] = M<R>::fma_(w, k[d], x[d]);
-    }
-}
-
-// One reverse step.  LOWREG recomputes each stage point when it is needed
-// (six right-hand sides instead of three) so that only one stage point is
-// live: the large systems would otherwise spill.
+// One reverse step.  LOWREG keeps the stage points y2, y3, y4 out of
+// registers, where the large systems would spill: they are computed once and
+// parked in LDS, in this thread's own column of `lds` (3 * D rows of
+// kAdjBlock entries, no sharing between threads, so no barrier), and each is
+// loaded back when its vector-Jacobian product needs it.
 template <class S, typename R, bool LOWREG>
 __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ], const R (&x)[S::D],
-                                         R (&lam)[S::D], R (&gp)[S::NP], R h, R h2, R h6, R h3) {
+                                         R (&lam)[S::D], R (&gp)[S::NP], R h, R h2, R h6, R h3,
+                                         R* lds = nullptr) {
     constexpr int D = S::D;
     R ys[3][D];  // y2, y3, y4 when !LOWREG
-    if constexpr (!LOWREG) {
+    if constexpr (LOWREG) {
+        R y[D], k[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) y[d] = x[d];
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            S::f(p, q, y, k);
+            const R w = (j == 2) ? h : h2;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                y[d] = M<R>::fma_(w, k[d], x[d]);
+                lds[(j * D + d) * kAdjBlock] = y[d];
+            }
+        }
+    } else {
         R k[D];
         S::f(p, q, x, k);
 #pragma unroll
@@ -108,7 +107,8 @@ __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ
             S::vjp(p, q, x, a, g, gp);
         } else if constexpr (LOWREG) {
             R y[D];
-            stage_point<S, R>(p, q, x, s, y, h, h2);
+#pragma unroll
+            for (int d = 0; d < D; ++d) y[d] = lds[((s - 2) * D + d) * kAdjBlock];
             S::vjp(p, q, y, a, g, gp);
         } else {
             S::vjp(p, q, ys[s - 2], a, g, gp);
@@ -122,8 +122,8 @@ __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ
         }
     };
     if constexpr (LOWREG) {
-        // kept as a loop so the scheduler cannot hoist the recomputation of
-        // later stage points above earlier VJPs (that would defeat LOWREG)
+        // kept as a loop so the scheduler cannot hoist the loads of later
+        // stage points above earlier VJPs (that would defeat LOWREG)
 #pragma unroll 1
         for (int s = 4; s >= 1; --s) stage(s);
     } else {
@@ -195,6 +195,11 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
     }
 
     // B. reverse sweep
+    R* stage_lds = nullptr;  // this thread's column of the stage-point store
+    if constexpr (LOWREG) {
+        __shared__ R stage_store[3 * D * kAdjBlock];
+        stage_lds = stage_store + threadIdx.x;
+    }
     R lam[D], gp[NP];
     R* lm = static_cast<R*>(a.lam);
 #pragma unroll
@@ -222,7 +227,7 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
         }
 #pragma unroll
         for (int t = T - 1; t >= 0; --t) {
-            if (t < len) vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3);
+            if (t < len) vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3, stage_lds);
         }
     }
     if (act) {
