@@ -188,7 +188,9 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             sb[d * n + i] = x[d];
-            if (KAHAN) subc[b * D * n + d * n + i] = c[d];
+            // the compensation is only needed to replay steps inside a
+            // sub-block, and a sub-block of one step replays none
+            if (KAHAN && T > 1) subc[b * D * n + d * n + i] = c[d];
         }
         if (b + 1 < nsub)
             for (int t = 0; t < T; ++t) rk4_step<S, R, KAHAN>(p, qd, x, c, h, h2, h6);
@@ -214,7 +216,7 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             xs[d] = sub[b * D * n + d * n + i];
-            cs[d] = KAHAN ? subc[b * D * n + d * n + i] : R(0);
+            cs[d] = (KAHAN && T > 1) ? subc[b * D * n + d * n + i] : R(0);
             tape[0][d] = xs[d];
         }
 #pragma unroll
