@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--rk4-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement (lorenz_8m)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work for the baseline")
     ap.add_argument("--extended", action="store_true",
                     help="also measure the other workloads (Lorenz 8M, HH ring 1M, adjoints, mixed batch)")
@@ -225,10 +226,15 @@ def main():
                        "(the FP32 run rounds them)" % w.nsteps)
         out["fp32_kahan_vs_fp64"] = acc
         del A32, A64
+    if not args.no_adjoint:
+        del B
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_line(A, I, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(e, w, args.cpu_seconds)
     if args.extended:
-        del B
+        if args.no_adjoint:
+            del B
         torch.cuda.empty_cache()
         out["extended"] = extended(A, I, torch, np)
     print(json.dumps(out), flush=True)
@@ -248,6 +254,55 @@ def _time_stream(torch, fn, reps=1):
         ts.append(a.elapsed_time(b))
     ts.sort()
     return ts[len(ts) // 2]
+
+
+def lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec):
+    """Adjoint of mean z(T) w.r.t. each particle's r on lorenz_8m (200 steps,
+    checkpoints every 50): checkpointed forward pass, then the reverse sweep."""
+    dev = st0.device
+    adj = w.adjoint
+    st = st0.clone()
+    comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
+    nb = A.adjoint_workspace_size(sysobj, st, adj["nsteps"], adj["K"], pparams=pp, pp_slot=w.pp_slot, comp=comp,
+                                  prec=prec)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    lam = torch.zeros_like(st)
+    mu = torch.empty_like(pp)
+    mug = torch.empty(3, dtype=torch.float64, device=dev)
+    # median of three: the first call of a kernel in the process also loads it
+    fwd = _time_stream(torch, lambda: A.integrate_checkpointed(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws,
+                                                                pparams=pp, pp_slot=w.pp_slot, comp=comp, prec=prec),
+                       reps=3)
+
+    def back():
+        lam.zero_()
+        lam[2].fill_(1.0 / w.n)
+        A.adjoint(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws, lam, mu=mu, mu_global=mug, pparams=pp,
+                  pp_slot=w.pp_slot, prec=prec)
+    back()
+    bwd = _time_stream(torch, back, reps=3)
+    return {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
+            "adjoint_steps_per_s": w.n * adj["nsteps"] / (bwd * 1e-3),
+            "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3)}
+
+
+def adjoint_line(A, I, torch):
+    """The metric's adjoint part on the workload that defines one (lorenz_8m:
+    8,388,608 particles, d(mean z(T))/d r_i over 200 steps, K = 50), in FP64
+    and FP32-Kahan."""
+    w = I.lorenz_8m()
+    e = I.generate(w)
+    sysobj = A.System("lorenz", 3, w.params)
+    out = {"workload": "lorenz_8m: 8388608 particles, per-particle r~U[0,50], d(mean z(T))/d r_i, "
+                       "200 RK4 steps, checkpoints every 50", "unit": "adjoint particle-steps/s"}
+    for prec in ("fp64", "fp32_kahan"):
+        dt_ = torch.float64 if prec == "fp64" else torch.float32
+        st0 = torch.as_tensor(e.state, dtype=dt_, device="cuda:0")
+        pp = torch.as_tensor(e.pparams, dtype=dt_, device="cuda:0").contiguous()
+        out[prec] = lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec)
+        del st0, pp
+    torch.cuda.empty_cache()
+    return out
 
 
 def extended(A, I, torch, np):
@@ -272,31 +327,8 @@ def extended(A, I, torch, np):
             ps = w.n * w.nsteps / (ms * 1e-3)
             tf = ps * FLOP_PER_STEP["lorenz"][prec] / 1e12
             r[prec] = {"particle_steps_per_s": ps, "ms": ms, "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[prec]}
-            # adjoint of mean z(T) w.r.t. each particle's r, 200 steps, K = 50
-            adj = w.adjoint
-            st = st0.clone()
-            comp = torch.zeros_like(st) if prec == "fp32_kahan" else None
-            nb = A.adjoint_workspace_size(sysobj, st, adj["nsteps"], adj["K"], pparams=pp, pp_slot=w.pp_slot, comp=comp,
-                                          prec=prec)
-            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-            lam = torch.zeros_like(st)
-            mu = torch.empty_like(pp)
-            mug = torch.empty(3, dtype=torch.float64, device=dev)
-            fwd = _time_stream(torch, lambda: A.integrate_checkpointed(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws,
-                                                                        pparams=pp, pp_slot=w.pp_slot, comp=comp,
-                                                                        prec=prec))
-
-            def back():
-                lam.zero_()
-                lam[2].fill_(1.0 / w.n)
-                A.adjoint(sysobj, st, 0.005, adj["nsteps"], adj["K"], ws, lam, mu=mu, mu_global=mug, pparams=pp,
-                          pp_slot=w.pp_slot, prec=prec)
-            back()
-            bwd = _time_stream(torch, back, reps=3)
-            r[prec]["adjoint"] = {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
-                                  "adjoint_steps_per_s": w.n * adj["nsteps"] / (bwd * 1e-3),
-                                  "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3)}
-            del st, st0, pp, comp, ws, lam, mu
+            r[prec]["adjoint"] = lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec)
+            del st, st0, pp, comp
         return r
 
     def hh1m():
