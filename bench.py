@@ -11,10 +11,14 @@ Workload (one "step" = one pass of the hot path over the ensemble):
 Prints one JSON line.  `value` is particle-RK4-steps/s of the whole step
 (P * 1000 / step time).  `roofline` is for the dominant kernel (the fused
 RK4 kernel): algorithmic FLOPs per launch / its average duration from HIP
-events recorded on the stream it runs on.  `cpu_baseline` times the CPU
-oracle (FP64, all host threads) on a bounded sample of the same ensemble.
+events recorded on the stream it runs on.  `fp64` is the same workload in
+double precision, `adjoint` the adjoint particle-steps/s of the Lorenz
+bifurcation workload (8M particles, 200 steps, checkpoints every 50), and
+`cpu_baseline` times the CPU oracle (FP64, all host threads) on a bounded
+sample of the ensemble.  --extended adds the other workloads.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+                  [--no-adjoint] [--extended]
 """
 from __future__ import annotations
 
@@ -79,6 +83,8 @@ def measured_traffic():
     if vals.get("source_hash") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
     return float(vals["traffic_bytes_per_launch"]), COUNTERS_FILE
+
+
 METRIC = "particle-RK4-steps/s (FP32-comp vs FP64) + % VALU peak; adjoint steps/s"
 
 
