@@ -13,7 +13,8 @@ Prints one JSON line.  `value` is particle-RK4-steps/s of the whole step
 RK4 kernel): algorithmic FLOPs per launch / its average duration from HIP
 events recorded on the stream it runs on.  `fp64` is the same workload in
 double precision, `adjoint` the adjoint particle-steps/s of the Lorenz
-bifurcation workload (8M particles, 200 steps, checkpoints every 50), and
+bifurcation workload (8M particles, 200 steps, checkpoints every 50) with
+the reverse sweep's fraction of the VALU peak, and
 `cpu_baseline` times the CPU oracle (FP64, all host threads) on a bounded
 sample of the ensemble.  --extended adds the other workloads.
 
@@ -48,6 +49,15 @@ FLOP_PER_STEP = {"wilson_cowan": {"fp32": 104, "fp32_kahan": 110, "fp64": 104},
                  "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68},
                  "hh_ring": {"fp32": 988, "fp32_kahan": 1033, "fp64": 988}}
 PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
+# One Lorenz adjoint step with checkpoints (same counting): the forward step
+# replayed from the checkpoint (68, or 77 compensated), the three stage points
+# (3 right-hand sides + 9 fma = 42), four products J(y_s)^T abar_s (12 with
+# sigma*a0 shared) with their parameter part (7) summed into g (3): 4 x 22 = 88,
+# the stage weights abar_{s-1} = fma(w, g_s, w' lam) (3 x 9 = 27), a = h/6 lam
+# (3) and lam += g (3): 68 + 163 = 231.  The kernel executes one more forward
+# step per step (the replay that fills its register tape), counted apart.
+ADJ_FLOP_PER_STEP = {"fp32": 231, "fp32_kahan": 240, "fp64": 231}
+ADJ_EXTRA_REPLAY_FLOP = {"fp32": 68, "fp32_kahan": 77, "fp64": 68}
 # Sources that define the dominant kernel and its launch shape (ff_api.hip
 # holds the default tuning); the HBM traffic measured with rocprofv3 counters
 # is reported only while their hash matches the one recorded next to the
@@ -287,9 +297,15 @@ def lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec):
                   pp_slot=w.pp_slot, prec=prec)
     back()
     bwd = _time_stream(torch, back, reps=3)
+    rate = w.n * adj["nsteps"] / (bwd * 1e-3)
+    tf = rate * ADJ_FLOP_PER_STEP[prec] / 1e12
+    tf_exec = rate * (ADJ_FLOP_PER_STEP[prec] + ADJ_EXTRA_REPLAY_FLOP[prec]) / 1e12
     return {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
-            "adjoint_steps_per_s": w.n * adj["nsteps"] / (bwd * 1e-3),
-            "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3)}
+            "adjoint_steps_per_s": rate,
+            "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3),
+            "flop_per_adjoint_step": ADJ_FLOP_PER_STEP[prec], "achieved_tflops": round(tf, 3),
+            "peak": PEAK_TFLOPS[prec], "frac": round(tf / PEAK_TFLOPS[prec], 4),
+            "frac_executed_incl_tape_replay": round(tf_exec / PEAK_TFLOPS[prec], 4)}
 
 
 def adjoint_line(A, I, torch):
