@@ -348,7 +348,11 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
  * workspace: device scratch of at least ff_groups_workspace_size() bytes (it
  * holds the tile counter of the launch), or NULL for a library-owned counter
  * (one per device: launches that use it concurrently on different streams of
- * one device race, and under stream capture a workspace must be passed). */
+ * one device race, and under stream capture a workspace must be passed).
+ * tuning: NULL takes the choice an earlier ff_autotune call in this process
+ * made for the same list (the same systems' kinds and sizes, precisions,
+ * particle counts, per-particle parameter counts and nsteps), and otherwise
+ * steps_per_launch = min(nsteps, 4096), one particle per thread, 256 threads. */
 typedef struct {
     ff_system_t sys;
     ff_batch b;

@@ -322,6 +322,22 @@ ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t 
     }
     Prepared P;
     if (ff_status s = prepare(groups, n_groups, t, &P)) return s;
+    if (!tuning) {
+        // the groups are valid now: take ff_autotune's choice for this list
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(signature(groups, n_groups, nsteps));
+            if (it != g_tune_cache.end()) {
+                t = it->second;
+                hit = true;
+            }
+        }
+        if (hit) {
+            P = Prepared();
+            if (ff_status s = prepare(groups, n_groups, t, &P)) return s;
+        }
+    }
     if (nsteps == 0 || P.tables.empty()) return FF_OK;
     if (workspace && workspace_bytes < 256) return fail(FF_E_NOMEM, "groups workspace needs 256 bytes");
     hipStream_t st = (hipStream_t)stream;

@@ -97,6 +97,15 @@ def test_autotune_picks_valid_shape_and_leaves_state(A):
         assert np.array_equal(a, b, equal_nan=True) and np.array_equal(ca, cb, equal_nan=True)
     t2 = A.autotune(groups, 200)  # cached
     assert (t2.steps_per_launch, t2.particles_per_thread, t2.block) == (t.steps_per_launch, t.particles_per_thread, t.block)
+    # without a tuning the batch takes the cached choice; still bitwise per-group
+    A.integrate_groups(groups, 200)
+    B2 = build(A, 0.002, torch.float32, True)
+    for b in B2:
+        for off, n, dt in zip(b["e"].offsets, b["e"].counts, b["e"].dts):
+            A.integrate(b["sys"], b["st"], dt, 200, n=n, offset=off, pparams=b["pp"], pp_slot=b["w"].pp_slot,
+                        comp=b["comp"], prec="fp32_kahan")
+    for (a, ca), (b, cb) in zip(snapshot(B), snapshot(B2)):
+        assert np.array_equal(a, b, equal_nan=True) and np.array_equal(ca, cb, equal_nan=True)
 
 
 def test_captured_frame_loop_replays_match_eager(A):
