@@ -19,6 +19,9 @@ class RK4Flow(torch.autograd.Function):
     def forward(ctx, x0, pparams, gparams, sys, dt, nsteps, K, pp_slot, kahan):
         if gparams is not None:
             sys.set_params([float(v) for v in gparams.detach().cpu().tolist()])
+        # the values this pass runs with: the system may be given others
+        # before backward (another flow on it, or the caller)
+        ctx.params = sys.get_params()
         x = x0.detach().clone().contiguous()
         pp = None if pparams is None else pparams.detach().contiguous()
         comp = torch.zeros_like(x) if kahan else None
@@ -37,9 +40,18 @@ class RK4Flow(torch.autograd.Function):
         pp = ctx.pp
         mu = None if pp is None else torch.empty_like(pp)
         mu_g = torch.empty(ctx.sys.n_params, dtype=torch.float64, device=lam.device) if ctx.has_g else None
-        # the batch only describes the particles here; its state is not read
-        A.adjoint(ctx.sys, lam, ctx.dt, ctx.nsteps, ctx.K, ctx.ws, lam, mu=mu, mu_global=mu_g,
-                  pparams=pp, pp_slot=ctx.pp_slot, prec="fp32_kahan" if ctx.kahan else None)
+        # the reverse sweep runs with the forward pass's parameters; the
+        # launch takes them by value, so the caller's are restored right after
+        current = ctx.sys.get_params()
+        if current != ctx.params:
+            ctx.sys.set_params(ctx.params)
+        try:
+            # the batch only describes the particles here; its state is not read
+            A.adjoint(ctx.sys, lam, ctx.dt, ctx.nsteps, ctx.K, ctx.ws, lam, mu=mu, mu_global=mu_g,
+                      pparams=pp, pp_slot=ctx.pp_slot, prec="fp32_kahan" if ctx.kahan else None)
+        finally:
+            if current != ctx.params:
+                ctx.sys.set_params(current)
         g_global = None if mu_g is None else mu_g.to(ctx.gdtype)
         return lam, mu, g_global, None, None, None, None, None, None
 

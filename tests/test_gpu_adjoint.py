@@ -166,6 +166,28 @@ def test_autograd_function(A, ora):
     assert rel(to_host(gg), rg, floor=1e-3 * np.abs(rg).max()).max() <= 1e-9
 
 
+def test_autograd_backward_uses_the_forward_parameters(A, ora):
+    """A second flow on the same system with other global parameters between
+    forward and backward must not change the first flow's gradients."""
+    from paper_1505_00344_amd.autograd import rk4_flow
+    n = 300
+    sysid, dim, params, x0, pp, slots, dt = case("lorenz", n)
+    sysobj = A.System(sysid, dim, params)
+    x = to_dev(x0, torch.float64).requires_grad_(True)
+    g = torch.tensor(params, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    xT = rk4_flow(x, sysobj, dt, 120, 30, pparams=to_dev(pp, torch.float64), pp_slot=slots, gparams=g)
+    other = [v * 1.25 for v in params]
+    rk4_flow(to_dev(x0, torch.float64), sysobj, dt, 20, 10, pparams=to_dev(pp, torch.float64), pp_slot=slots,
+             gparams=torch.tensor(other, dtype=torch.float64, device="cuda:0"))
+    gx, gg = torch.autograd.grad(xT[2].sum(), (x, g))
+    lamT = np.zeros((dim, n))
+    lamT[2] = 1.0
+    rl, _, rg = ora.adjoint(sysid, params, x0, lamT, dt, 120, pp_slot=slots, pparams=pp)
+    assert rel(to_host(gx), rl, floor=1e-3).max() <= 1e-9
+    assert rel(to_host(gg), rg, floor=1e-3 * np.abs(rg).max()).max() <= 1e-9
+    assert sysobj.get_params() == other  # the caller's values are back
+
+
 def test_zero_steps_adjoint_is_identity(A):
     sysobj = A.System("lorenz", 3, I.LORENZ_PARAMS)
     x = torch.ones((3, 100), dtype=torch.float64, device="cuda:0")
