@@ -162,6 +162,7 @@ def make_batch(state: torch.Tensor, n: Optional[int] = None, pparams: Optional[t
         if comp.shape != state.shape:
             raise ValueError("comp must have the shape of state")
         b.comp = comp.data_ptr() + offset * esz
+    b._keep = (state, pparams, comp)  # the tensors behind the pointers live as long as the batch
     return b
 
 
@@ -356,13 +357,15 @@ def adjoint(sys: System, state: torch.Tensor, dt: float, nsteps: int, K: int, wo
 
 
 def make_groups(specs) -> "ctypes.Array":
-    """specs: iterable of (System, Batch, dt)."""
+    """specs: iterable of (System, Batch, dt).  The array keeps the systems
+    (whose handles it holds) and the batches' tensors alive."""
     specs = list(specs)
     arr = (Group * len(specs))()
     for g, (sys, b, dt) in zip(arr, specs):
         g.sys = sys.handle
         g.b = b
         g.dt_signed = float(dt)
+    arr._keep = [(sys, getattr(b, "_keep", None)) for sys, b, _ in specs]
     return arr
 
 

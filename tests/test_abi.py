@@ -167,6 +167,23 @@ def test_groups_validation(L):
     assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == 0  # nothing to do
 
 
+def test_groups_keep_their_systems_alive(L):
+    """The group array holds raw system handles: the System objects must live
+    as long as the array, or a later call would use a destroyed handle."""
+    import gc
+    import weakref
+
+    from paper_1505_00344_amd import api as A
+    g = A.make_groups([(A.System("lorenz", 3, [10, 28, 8 / 3]), _batch(), 0.0)])
+    ref = weakref.ref(g._keep[0][0])
+    gc.collect()
+    assert ref() is not None
+    assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == 0
+    del g
+    gc.collect()
+    assert ref() is None
+
+
 def test_render_workspace_size_selects_the_path(L):
     from paper_1505_00344_amd import api as A
     size = A.render_workspace_size
