@@ -49,6 +49,7 @@ FLOP_PER_STEP = {"wilson_cowan": {"fp32": 104, "fp32_kahan": 110, "fp64": 104},
                  "lorenz": {"fp32": 68, "fp32_kahan": 77, "fp64": 68},
                  "hh_ring": {"fp32": 988, "fp32_kahan": 1033, "fp64": 988}}
 PEAK_TFLOPS = {"fp32": 157.3, "fp32_kahan": 157.3, "fp64": 78.6}
+HBM_PEAK_TBS = 8.0
 # One Lorenz adjoint step with checkpoints (same counting): the forward step
 # replayed from the checkpoint (68, or 77 compensated), the three stage points
 # (3 right-hand sides + 9 fma = 42), four products J(y_s)^T abar_s (12 with
@@ -562,8 +563,34 @@ def extended(A, I, torch, np):
             r[f"expr_wc_2m_forward_{prec}"] = out_
         return r
 
+    def one_step_per_launch():
+        """The paper's launch pattern (one RK4 step per kernel launch): each
+        launch reads and writes the whole state, so it is bound by HBM.
+        lorenz_8m in FP32: 3 state values read and written and r read, 28 B
+        per particle-step, against the fused kernel on the same input."""
+        w = I.lorenz_8m()
+        e = I.generate(w)
+        sysobj = A.System("lorenz", 3, w.params)
+        st = torch.as_tensor(e.state, dtype=torch.float32, device=dev).contiguous()
+        pp = torch.as_tensor(e.pparams, dtype=torch.float32, device=dev).contiguous()
+        nl = 200
+        r = {}
+        for name, tun in (("one_step_per_launch", (1, 1, 256)), ("fused", None)):
+            def go():
+                A.integrate(sysobj, st, 0.005, nl, pparams=pp, pp_slot=w.pp_slot, tuning=tun, prec="fp32")
+            go()
+            ms = _time_stream(torch, go, reps=3)
+            r[name] = {"ms_per_step": ms / nl, "particle_steps_per_s": w.n * nl / (ms * 1e-3)}
+        bytes_per_launch = w.n * (2 * 3 * 4 + 4)
+        tbs = bytes_per_launch / (r["one_step_per_launch"]["ms_per_step"] * 1e-3) / 1e12
+        r["one_step_per_launch"].update({"bytes_per_launch": bytes_per_launch, "achieved_TB_per_s": tbs,
+                                         "frac_of_hbm_peak": tbs / HBM_PEAK_TBS})
+        r["fused_speedup"] = r["one_step_per_launch"]["ms_per_step"] / r["fused"]["ms_per_step"]
+        return r
+
     for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed),
-                     ("reset_record_render_expressions", reset_record_render_expressions)):
+                     ("reset_record_render_expressions", reset_record_render_expressions),
+                     ("one_step_per_launch", one_step_per_launch)):
         try:
             res[name] = fn()
         except Exception as ex:  # report and continue with the next workload
