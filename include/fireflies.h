@@ -367,7 +367,15 @@ ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t 
 /* Pick steps_per_launch, particles_per_thread and block for a group list by
  * timing candidate launches (on copies of the groups' state, which is left
  * unchanged).  steps_per_launch is searched in [10, min(500, nsteps)].
- * Synchronises the stream.  *out receives the choice. */
+ * Synchronises the stream.  *out receives the choice.  Choices are cached
+ * per list for the process; a list already tuned returns at once.  When the
+ * environment variable FF_AUTOTUNE_CACHE names a file, the cache is also
+ * read from it (at the first lookup of the process) and each new choice is
+ * appended to it as a line "<signature> <steps_per_launch>
+ * <particles_per_thread> <block>", where the signature is nsteps followed,
+ * per group, by "|rhs,dim,prec,n,n_pp" (decimal).  The file is meant for one
+ * kind of GPU; unreadable or malformed lines are skipped, and a failed write
+ * is ignored. */
 ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, ff_tuning* out,
                       void* stream);
 

@@ -12,9 +12,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -278,8 +281,60 @@ ff_status run_prepared(Prepared& P, int64_t nsteps, const ff_tuning& t, unsigned
     return FF_OK;
 }
 
+// Autotune choices per group list.  When the environment variable
+// FF_AUTOTUNE_CACHE names a file, its lines "<signature> <steps_per_launch>
+// <particles_per_thread> <block>" are read at the first lookup of the process
+// (malformed lines are skipped) and every new choice is appended to it.  The
+// file only saves tuning time: a write that fails is ignored.
 std::mutex g_tune_mu;
 std::map<std::string, ff_tuning> g_tune_cache;
+bool g_tune_file_read = false;
+
+const char* tune_file() {
+    const char* p = std::getenv("FF_AUTOTUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+bool valid_tuning(long long s, int ppt, int block) {
+    return s >= 1 && s <= 0x7fffffffLL && (ppt == 1 || ppt == 2 || ppt == 4) && block >= 64 && block <= 256 &&
+           block % 64 == 0;
+}
+
+// Caller holds g_tune_mu.
+void read_tune_file() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = tune_file();
+    if (!path) return;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ss(line);
+        std::string key;
+        long long steps = 0;
+        int ppt = 0, block = 0;
+        if (!(ss >> key >> steps >> ppt >> block) || !valid_tuning(steps, ppt, block)) continue;
+        g_tune_cache[key] = ff_tuning{(int32_t)steps, ppt, block};
+    }
+}
+
+// Caller holds g_tune_mu.
+bool find_tuning(const std::string& key, ff_tuning* t) {
+    read_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+// Caller holds g_tune_mu.
+void store_tuning(const std::string& key, const ff_tuning& t) {
+    g_tune_cache[key] = t;
+    if (const char* path = tune_file()) {
+        std::ofstream out(path, std::ios::app);
+        out << key << ' ' << t.steps_per_launch << ' ' << t.particles_per_thread << ' ' << t.block << '\n';
+    }
+}
 
 std::string signature(const ff_group* groups, int32_t n_groups, int64_t nsteps) {
     std::string s = std::to_string(nsteps);
@@ -327,11 +382,7 @@ ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t 
         bool hit = false;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_tune_cache.find(signature(groups, n_groups, nsteps));
-            if (it != g_tune_cache.end()) {
-                t = it->second;
-                hit = true;
-            }
+            hit = find_tuning(signature(groups, n_groups, nsteps), &t);
         }
         if (hit) {
             P = Prepared();
@@ -364,11 +415,7 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
     const std::string key = signature(groups, n_groups, nsteps);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            *out = it->second;
-            return FF_OK;
-        }
+        if (find_tuning(key, out)) return FF_OK;
     }
     hipStream_t st = (hipStream_t)stream;
     unsigned int* counter = nullptr;
@@ -452,7 +499,7 @@ ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, 
     cleanup();
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = bestt;
+        store_tuning(key, bestt);
     }
     *out = bestt;
     return FF_OK;

@@ -184,6 +184,37 @@ def test_groups_keep_their_systems_alive(L):
     assert ref() is None
 
 
+def test_autotune_reads_its_cache_file(tmp_path):
+    """ff_autotune answers from the FF_AUTOTUNE_CACHE file when it holds the
+    group list (a hit returns before any device call; malformed lines and
+    invalid launch shapes are skipped).  Fresh process: the file is read once."""
+    import subprocess
+    import sys
+
+    from paper_1505_00344_amd import _ffi
+    key = f"50|{_ffi.FF_RHS_LORENZ},3,{_ffi.FF_FP64},10,0"
+    cache = tmp_path / "tune.txt"
+    cache.write_text("not a tuning line\n"
+                     f"{key} 37 4 64\n"
+                     f"7|9,9,9,9,9 20 2 100\n"   # block 100: invalid, skipped
+                     f"{key} 37 3 64\n")         # 3 particles per thread: invalid, skipped (else it would win)
+    code = (
+        "import ctypes, sys\n"
+        f"sys.path.insert(0, {os.path.join(ROOT, 'tests')!r})\n"
+        "from test_abi import _batch\n"
+        "from paper_1505_00344_amd import _ffi, api as A\n"
+        "L = _ffi.lib()\n"
+        "s = A.System('lorenz', 3, [10, 28, 8 / 3])\n"
+        "g = A.make_groups([(s, _batch(), 0.01)])\n"
+        "t = _ffi.Tuning()\n"
+        "rc = L.ff_autotune(g, 1, 50, ctypes.byref(t), None)\n"
+        "print(rc, t.steps_per_launch, t.particles_per_thread, t.block)\n")
+    env = dict(os.environ, FF_AUTOTUNE_CACHE=str(cache), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["0", "37", "4", "64"]
+
+
 def test_render_workspace_size_selects_the_path(L):
     from paper_1505_00344_amd import api as A
     size = A.render_workspace_size

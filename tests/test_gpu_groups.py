@@ -86,11 +86,17 @@ def test_batch_fp64_lorenz_groups_match_oracle(A, ora):
             assert np.array_equal(g[:, fin], ref[:, fin])
 
 
-def test_autotune_picks_valid_shape_and_leaves_state(A):
+def test_autotune_picks_valid_shape_and_leaves_state(A, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FF_AUTOTUNE_CACHE", str(cache))
     B = build(A, 0.002, torch.float32, True)
     before = snapshot(B)
     groups = A.make_groups(specs(A, B, "fp32_kahan"))
     t = A.autotune(groups, 200)
+    # the new choice is appended to the cache file
+    line = cache.read_text().split("\n")[0].split()
+    assert line[0].startswith("200|") and len(line[0].split("|")) == 25
+    assert [int(v) for v in line[1:]] == [t.steps_per_launch, t.particles_per_thread, t.block]
     assert 10 <= t.steps_per_launch <= 200 and t.particles_per_thread in (1, 2, 4) and t.block in (128, 256)
     after = snapshot(B)
     for (a, ca), (b, cb) in zip(before, after):
