@@ -19,7 +19,7 @@ the reverse sweep's fraction of the VALU peak, and
 sample of the ensemble.  --extended adds the other workloads.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
-                  [--no-adjoint] [--extended]
+                  [--no-adjoint] [--extended [--only WORKLOAD]]
 """
 from __future__ import annotations
 
@@ -112,6 +112,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work for the baseline")
     ap.add_argument("--extended", action="store_true",
                     help="also measure the other workloads (Lorenz 8M, HH ring 1M, adjoints, mixed batch)")
+    ap.add_argument("--only", default=None,
+                    help="with --extended: measure only this workload (lorenz_8m, hh_ring_1m, mixed_batch, "
+                         "reset_record_render_expressions, one_step_per_launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -253,7 +256,7 @@ def main():
         if args.no_adjoint:
             del B
         torch.cuda.empty_cache()
-        out["extended"] = extended(A, I, torch, np)
+        out["extended"] = extended(A, I, torch, np, only=args.only)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -328,7 +331,7 @@ def adjoint_line(A, I, torch):
     return out
 
 
-def extended(A, I, torch, np):
+def extended(A, I, torch, np, only=None):
     """Throughput of the other workloads (each run once after a warm-up)."""
     dev = torch.device("cuda:0")
     res = {}
@@ -591,6 +594,8 @@ def extended(A, I, torch, np):
     for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed),
                      ("reset_record_render_expressions", reset_record_render_expressions),
                      ("one_step_per_launch", one_step_per_launch)):
+        if only is not None and name != only:
+            continue
         try:
             res[name] = fn()
         except Exception as ex:  # report and continue with the next workload
