@@ -120,15 +120,27 @@ typedef struct {
     int32_t block;
 } ff_tuning;
 
+/* Library plumbing, not part of the paper's method: the ABI version this
+ * header describes (FF_ABI_VERSION), and the text of the last error on the
+ * calling thread (valid until the next ff_* call on this thread; never
+ * NULL). */
 int32_t ff_abi_version(void);
-
-/* Text of the last error on the calling thread; valid until the next ff_*
- * call on this thread.  Never NULL. */
 const char* ff_last_error(void);
 
-/* Create a system: right-hand side, dimension, parameter count and default
- * global parameter values (host, n_params doubles).  Host-only: touches no
- * device.  *out receives the handle (release it with ff_system_destroy). */
+/* Create a system (Appendix A, "State Variables" and "Parameters": the N
+ * state variables each with the right-hand side of its ODE, and the
+ * parameters each with a default value).  rhs selects a compiled-in
+ * right-hand side (ff_rhs; expression systems come from
+ * ff_system_create_expr), dim is N, params holds the n_params default global
+ * values (host, copied).  The variables' bounds and the parameters' allowed
+ * ranges are not part of a system: the bounds are arguments of
+ * ff_integrate_reset, and ranges are the caller's business.  FF_E_INVALID
+ * when rhs is unknown, dim or n_params does not fit rhs (see ff_rhs above),
+ * or params or out is NULL; FF_E_UNSUPPORTED for a Hodgkin-Huxley ring of
+ * other than 1 or 3 neurons.  Host-only: touches no device.  *out receives
+ * the handle (NULL on failure), owned by the library until
+ * ff_system_destroy releases it; destroying NULL does nothing and returns
+ * FF_OK, and a handle must not be used after it is destroyed. */
 ff_status ff_system_create(int32_t rhs, int32_t dim, int32_t n_params, const double* params,
                            ff_system_t* out);
 ff_status ff_system_destroy(ff_system_t sys);
@@ -137,6 +149,10 @@ ff_status ff_system_destroy(ff_system_t sys);
  * paper's live slider (Appendix A.2).  Takes effect for calls enqueued
  * afterwards. */
 ff_status ff_system_set_params(ff_system_t sys, const double* params, int32_t n_params);
+/* Read back the current global parameter values (host array of n_params
+ * doubles, n_params equal to the system's count) and the system's kind,
+ * dimension and parameter count (Appendix A, "State Variables" and
+ * "Parameters"); host-only. */
 ff_status ff_system_get_params(ff_system_t sys, double* params, int32_t n_params);
 ff_status ff_system_info(ff_system_t sys, int32_t* rhs, int32_t* dim, int32_t* n_params);
 
@@ -318,9 +334,13 @@ ff_status ff_render_image(ff_system_t sys, const ff_batch* b, const ff_render* r
                           uint64_t* n_culled, int32_t accumulate, void* workspace,
                           size_t workspace_bytes, void* stream);
 
-/* Discrete adjoint (exact gradient of the RK4 map above with respect to the
- * initial state and the parameters; the Kahan update is differentiated as
- * exact addition).  Usage: ff_integrate_checkpointed() advances the batch
+/* Discrete adjoint.  The paper defines no adjoint or gradient: these three
+ * calls extend its method with the exact gradient of the RK4 map above
+ * (Section 2.1; Appendix A.1) with respect to the initial state and the
+ * parameters, for sensitivities of quantities read off the ensemble (e.g.
+ * how the mean of a state variable at time T changes with each particle's
+ * bifurcation parameter).  The Kahan update is differentiated as exact
+ * addition.  Usage: ff_integrate_checkpointed() advances the batch
  * like ff_integrate() and stores the state (and compensation) every K steps
  * in `workspace`; then ff_adjoint() walks the segments backwards, recomputing
  * each segment from its checkpoint.
@@ -341,7 +361,10 @@ ff_status ff_adjoint(ff_system_t sys, const ff_batch* b, double dt_signed, int64
                      int32_t K, void* workspace, size_t workspace_bytes, void* lambda, void* mu,
                      double* mu_global, void* stream);
 
-/* Ragged batch: several particle groups (each with its own system, slice,
+/* Ragged batch (Appendix A, "Particle Group": a system holds one or more
+ * groups, each with its own particle count and direction in time, forward or
+ * backward; Appendix A.2: the main loop advances every group once per frame
+ * before rendering): several groups (each with its own system, slice,
  * precision and signed step) advanced nsteps in one persistent launch per
  * steps_per_launch.  Every group must use FF_FP32 or FF_FP32_KAHAN or every
  * group FF_FP64.  Results are bitwise equal to ff_integrate on each group.
@@ -364,8 +387,10 @@ ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t 
                               const ff_tuning* tuning, void* workspace, size_t workspace_bytes,
                               void* stream);
 
-/* Pick steps_per_launch, particles_per_thread and block for a group list by
- * timing candidate launches (on copies of the groups' state, which is left
+/* Launch-shape search for ff_integrate_groups.  Not part of the paper's
+ * method (it changes no result: every shape gives the same bits), only of how
+ * fast this library runs it.  Picks steps_per_launch, particles_per_thread and
+ * block for a group list by timing candidate launches (on copies of the groups' state, which is left
  * unchanged).  steps_per_launch is searched in [10, min(500, nsteps)].
  * Synchronises the stream.  *out receives the choice.  Choices are cached
  * per list for the process; a list already tuned returns at once.  When the

@@ -19,24 +19,29 @@ template <> struct M<double> {
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     // 1/x: the hardware estimate (v_rcp_f64) refined by two Newton steps,
     // within 1 ulp (not always the correctly rounded quotient, which costs
-    // about twice the instructions); for zero, subnormal and infinite x the
-    // estimate itself is returned, which is IEEE's 1/x there (+-inf, +-0).
-    static constexpr int kZeroSubInf = (1 << 2) | (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7) | (1 << 9);
+    // about twice the instructions).  Where the estimate is +-0 or +-inf
+    // (x infinite or zero, or |x| < 2^-1024 so that 1/x overflows) it is
+    // IEEE's 1/x and is returned as it is, since a Newton step would turn it
+    // into NaN; every other x, subnormal ones included, takes the refined
+    // value.
+    static constexpr int kZeroInf = (1 << 2) | (1 << 5) | (1 << 6) | (1 << 9);
     static __device__ __forceinline__ double rcp_(double x) {
         const double r0 = __builtin_amdgcn_rcp(x);
         double r = __builtin_fma(__builtin_fma(-x, r0, 1.0), r0, r0);
         r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
-        return __builtin_amdgcn_class(x, kZeroSubInf) ? r0 : r;
+        return __builtin_amdgcn_class(r0, kZeroInf) ? r0 : r;
     }
     // a/b: a times that reciprocal with one residual correction (within
-    // 1 ulp); the same special cases fall back to a * estimate.
+    // 1 ulp).  Where the estimate is +-0 or +-inf the result is a times it:
+    // IEEE's a/b for b zero or infinite, and for |b| < 2^-1024 unless |a|
+    // is small enough for a/b to be finite (then +-inf or NaN instead).
     static __device__ __forceinline__ double div_(double a, double b) {
         const double r0 = __builtin_amdgcn_rcp(b);
         double r = __builtin_fma(__builtin_fma(-b, r0, 1.0), r0, r0);
         r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
         const double q = a * r;
         const double qc = __builtin_fma(__builtin_fma(-b, q, a), r, q);
-        return __builtin_amdgcn_class(b, kZeroSubInf) ? a * r0 : qc;
+        return __builtin_amdgcn_class(r0, kZeroInf) ? a * r0 : qc;
     }
 };
 // Single precision.  By default (FF_FAST_F32 = 1) the exponential is the

@@ -252,11 +252,29 @@ template <typename R, int N> struct HHRing {
             o[5 * j + 4] = hh_gate(p[10] * q.tv, p[11], s);
         }
     }
-    // psi'(u) = (expm1(u) - u e^u) / expm1(u)^2, psi'(0) = -1/2.
+    // psi'(u) = (expm1(u) - u e^u) / expm1(u)^2, psi'(0) = -1/2.  The
+    // numerator is a difference of two terms of size |u| that cancel to
+    // -u^2/2, so in fast single precision |u| < 1/2 takes the derivative of
+    // the Bernoulli series instead, -1/2 + u/6 - u^3/180 + u^5/5040 -
+    // u^7/151200 (the next term, u^9/4790016, is below 4.1e-10 there), and
+    // the rest the hardware exponential (cancellation there costs a few
+    // ulp).  Both are computed and one is selected.
     static __device__ __forceinline__ R dpsi(R u) {
-        const R em1 = M<R>::expm1_(u);
-        const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
-        return (u == R(0)) ? R(-0.5) : d;
+        if constexpr (M<R>::kFast) {
+            const R w = u * u;
+            const R series = M<R>::fma_(
+                u, M<R>::fma_(w, M<R>::fma_(w, M<R>::fma_(w, R(-1.0 / 151200.0), R(1.0 / 5040.0)), R(-1.0 / 180.0)),
+                              R(1.0 / 6.0)),
+                R(-0.5));
+            const R e = M<R>::exp2_(u * R(kLog2e));
+            const R em1 = e - R(1);
+            const R direct = (em1 - u * e) * M<R>::rcp_(em1 * em1);
+            return __builtin_fabsf(u) < R(0.5) ? series : direct;
+        } else {
+            const R em1 = M<R>::expm1_(u);
+            const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
+            return (u == R(0)) ? R(-0.5) : d;
+        }
     }
     static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {

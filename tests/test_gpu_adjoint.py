@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import tolerances as tol
-from helpers import api, f32_inputs, quantiles, to_dev, to_host
+from helpers import api, f32_inputs, quantiles, record, to_dev, to_host
 from paper_1505_00344_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -119,12 +119,19 @@ def test_linear_adjoint_closed_form(A):
     assert np.allclose(lam0, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
 @pytest.mark.parametrize("name", ["lorenz", "hh"])
-def test_adjoint_bitwise_independent_of_K(A, name):
+def test_adjoint_bitwise_independent_of_K(A, name, prec):
+    # in FP32-Kahan the HH ring runs the register-capped reverse kernel
     n, nsteps = (1000, 120) if name == "lorenz" else (200, 60)
     sysid, dim, params, x0, pp, slots, dt = case(name, n)
     lamT = np.random.default_rng(2).normal(size=x0.shape)
-    outs = [gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, nsteps, K, pp, slots) for K in (nsteps, 7, 50)]
+    kw = {}
+    if prec == "fp32_kahan":
+        x0, pp, lamT = x0.astype(np.float32), pp.astype(np.float32), lamT.astype(np.float32)
+        dt = float(np.float32(dt))
+        kw = dict(dtype=torch.float32, kahan=True)
+    outs = [gpu_adjoint(A, sysid, dim, params, x0, lamT, dt, nsteps, K, pp, slots, **kw) for K in (nsteps, 7, 50)]
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
@@ -144,6 +151,58 @@ def test_kahan_adjoint_vs_fp64(A, ora):
     _, ref_mu, _ = ora.adjoint(sysid, params, x0, lamT, dt32, 200, pp_slot=slots, pparams=pp)
     e = rel(mu32[0].astype(np.float64), ref_mu[0], floor=1e-3 * max(1.0, np.abs(ref_mu).max()))
     assert np.quantile(e, 0.99) <= tol.ADJ_FP32_P99, quantiles(e)
+
+
+def test_hh_ring_kahan_adjoint_vs_fp64(A, ora):
+    # the HH ring workload's gradient (Section 3, the ring of Eqs. hh_v to
+    # hh_s): d(mean V1(T))/d(gsyn_i, Iext_i) over 2000 steps, checkpoints
+    # every 100, FP32-Kahan (the register-capped reverse kernel) against the
+    # oracle's FP64 adjoint from the same single-precision inputs and step
+    n = 2048 + 5
+    sysid, dim, params, x0, pp, slots, dt = case("hh", n)
+    x0 = f32_inputs(x0)
+    pp = f32_inputs(pp)
+    dt32 = float(np.float32(dt))
+    lamT = np.zeros((15, n))
+    lamT[0] = float(np.float32(1.0 / n))
+    xT, _, mu32, _ = gpu_adjoint(A, sysid, dim, params, x0.astype(np.float32), lamT.astype(np.float32), dt32,
+                                 2000, 100, pp.astype(np.float32), slots, dtype=torch.float32, kahan=True,
+                                 want_global=False)
+    assert np.all(np.isfinite(xT)) and np.all(np.isfinite(mu32))
+    _, ref_mu, _ = ora.adjoint(sysid, params, x0, lamT, dt32, 2000, pp_slot=slots, pparams=pp)
+    e = rel(mu32.astype(np.float64), ref_mu, floor=tol.ADJ_FLOOR * np.abs(ref_mu).max())
+    record("hh_adjoint_fp32_kahan_vs_fp64", err=quantiles(e.ravel()))
+    assert np.quantile(e, 0.99) <= tol.ADJ_FP32_P99, quantiles(e.ravel())
+
+
+def test_hh_kahan_adjoint_near_the_rate_singularities(A, ora):
+    # alpha_m and alpha_n are psi(u) = u/(e^u - 1) at u = -(V+40)/10 and
+    # -(V+55)/10 (Section 3's gate equations): their derivative cancels badly
+    # near u = 0 in single precision.  One step from V within 1e-4..3 mV of
+    # -40 and -55 mV, with the adjoint seeded on the m and n gates of the
+    # first neuron, the FP32-Kahan gradient with respect to that neuron's V
+    # must stay within 1e-5 of the FP64 oracle's (relative, floor 1e-3 of the
+    # largest).
+    offs = np.array([0.0, 1e-4, -1e-4, 1e-3, -1e-3, 1e-2, -1e-2, 0.1, -0.1, 1.0, -1.0, 3.0, -3.0])
+    v0 = np.concatenate([-40.0 + offs, -55.0 + offs])
+    n = len(v0)
+    x0 = np.empty((15, n))
+    for j in range(3):
+        x0[5 * j:5 * j + 5] = np.array([[-62.0], [0.3], [0.5], [0.4], [0.2]])
+    x0[0] = v0
+    x0 = f32_inputs(x0)
+    pp = f32_inputs(np.tile(np.array([[0.5], [10.0]]), (1, n)))
+    w = I.hh_ring_1m(n=1)
+    lamT = np.zeros((15, n))
+    lamT[1] = 1.0
+    lamT[3] = 1.0
+    dt32 = float(np.float32(0.01))
+    _, lam0, _, _ = gpu_adjoint(A, I.HH_RING, 15, w.params, x0.astype(np.float32), lamT.astype(np.float32), dt32,
+                                1, 1, pp.astype(np.float32), w.pp_slot, dtype=torch.float32, kahan=True,
+                                want_global=False)
+    ref_l, _, _ = ora.adjoint(ora.HH_RING, w.params, x0, lamT, dt32, 1, pp_slot=w.pp_slot, pparams=pp)
+    e = rel(lam0[0].astype(np.float64), ref_l[0], floor=1e-3 * np.abs(ref_l[0]).max())
+    assert e.max() <= 1e-5, (v0[np.argmax(e)], quantiles(e))
 
 
 def test_autograd_function(A, ora):

@@ -31,8 +31,27 @@ FP32_LORENZ_BIF_P99 = 1e-3
 KAHAN_LORENZ_BIF_MEDIAN = 1e-6
 KAHAN_LORENZ_BIF_P99 = 1e-4
 FP32_WC_P99 = 1e-4                   # Wilson-Cowan, 1000 steps
-KAHAN_WC_MEDIAN = 1e-7
+KAHAN_WC_MEDIAN = 1e-7              # contracting (forward) groups only
 KAHAN_WC_P99 = 1e-5
+# Expanding (backward) Wilson-Cowan groups.  Integrated backward, the flow
+# expands areas: most particles leave the unit square, both sigmoids saturate
+# to exactly 0 or 1, the right-hand side becomes affine and the state grows
+# like e^{|t|}.  The relative error of such a particle is then set by the
+# single-precision rounding of the step weight h/6 (relative rho,
+# |rho| <= u = 2^-24), which every step's growth factor carries: after the
+# elapsed time T = nsteps*|h| it is T*|rho| plus smaller terms (h = -0.01,
+# 1000 steps: rho = -2.33e-8, T*|rho| = 2.33e-7).  The median bound is the
+# worst case over h, T*u (5.96e-7 at T = 10); the contracting groups' median
+# bound does not apply.  The p99 bound stays KAHAN_WC_P99, plain FP32 keeps
+# FP32_WC_P99, and Kahan must halve plain FP32's median (KAHAN_GAIN).
+UNIT_ROUNDOFF_F32 = 2.0 ** -24
+
+
+def kahan_wc_expanding_median(nsteps, h):
+    """Median bound of FP32-Kahan vs FP64 on an expanding Wilson-Cowan group."""
+    return nsteps * abs(h) * UNIT_ROUNDOFF_F32
+
+
 KAHAN_HH_MEDIAN = 1e-6               # HH ring, 2000 steps
 KAHAN_HH_P99 = 1e-4
 KAHAN_HH_MAX = 1e-3
