@@ -52,6 +52,8 @@ extern "C" {
 
 #define FF_ABI_VERSION 2
 #define FF_MAX_PP 4 /* per-particle parameters per batch */
+/* bytes of device scratch held by ff_project_histogram_noalloc (per GPU) */
+#define FF_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 
 typedef enum {
     FF_OK = 0,
@@ -289,6 +291,24 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
                                double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
                                int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* The same projection for callers that cannot allocate device memory (code
+ * under stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): arguments and results as ff_project_histogram without a
+ * workspace, and no call of this function allocates.  Its scratch is a static
+ * device array of FF_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code
+ * object and held until the process ends; a projection needing more
+ * (ff_histogram_workspace_size() > FF_NOALLOC_SCRATCH_BYTES: beyond about
+ * 11M particles on a 1024 x 1024 grid, fewer on larger grids; grids of at
+ * most 16384 bins need no scratch at all) returns
+ * FF_E_NOMEM before anything is enqueued.  Every call on one GPU shares that
+ * array: calls that overlap on one device (different streams, host threads)
+ * race and must be ordered by the caller.  Nothing in it needs to start at
+ * zero.  The first call on a device looks the array's address up there. */
+ff_status ff_project_histogram_noalloc(ff_system_t sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
+                                       double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
+                                       int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
+                                       void* stream);
 
 /* Particle image: the paper's render technique (Appendix A "Render
  * Technique": 2D or perspective 3D projection onto chosen axes, colour fixed

@@ -75,6 +75,8 @@ SIGNATURES = {
     "ff_histogram_workspace_size": (_i32, [_i64, _i32, _i32, _c.POINTER(_sz)]),
     "ff_project_histogram": (_i32, [_vp, _c.POINTER(Batch), _i32, _i32, _dbl, _dbl, _dbl, _dbl,
                                     _i32, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),
+    "ff_project_histogram_noalloc": (_i32, [_vp, _c.POINTER(Batch), _i32, _i32, _dbl, _dbl, _dbl, _dbl,
+                                            _i32, _i32, _vp, _vp, _i32, _vp]),
     "ff_adjoint_workspace_size": (_i32, [_vp, _c.POINTER(Batch), _i64, _i32, _c.POINTER(_sz)]),
     "ff_integrate_checkpointed": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _i32, _vp, _sz, _vp]),
     "ff_adjoint": (_i32, [_vp, _c.POINTER(Batch), _dbl, _i64, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),

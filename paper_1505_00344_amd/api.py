@@ -270,6 +270,28 @@ def project_histogram(sys: System, state: torch.Tensor, axis_x: int, axis_y: int
     return hist, n_dropped
 
 
+def project_histogram_noalloc(sys: System, state: torch.Tensor, axis_x: int, axis_y: int, x_range, y_range,
+                              nx: int, ny: int, *, hist: Optional[torch.Tensor] = None,
+                              n_dropped: Optional[torch.Tensor] = None, accumulate: bool = False, n=None,
+                              pparams=None, pp_slot=(), prec=None, stream=None, offset=0):
+    """ff_project_histogram_noalloc: as project_histogram, with the library's
+    static scratch instead of a workspace (hist and n_dropped must be passed
+    in for a call that allocates nothing at all)."""
+    b = make_batch(state, n, pparams, pp_slot, None, prec if prec != "fp32_kahan" else "fp32", offset)
+    dev = state.device
+    if hist is None:
+        hist = torch.empty((ny, nx), dtype=torch.int32, device=dev)
+    if n_dropped is None:
+        n_dropped = torch.empty(1, dtype=torch.int64, device=dev)
+    _check_out(hist, "hist", (ny, nx), (torch.int32,))
+    _check_out(n_dropped, "n_dropped", 1, (torch.int64,), min_numel=True)
+    _check_gpu(state, hist=hist, n_dropped=n_dropped)
+    call("ff_project_histogram_noalloc", sys.handle, ctypes.byref(b), int(axis_x), int(axis_y),
+         float(x_range[0]), float(x_range[1]), float(y_range[0]), float(y_range[1]), int(nx), int(ny),
+         hist.data_ptr(), n_dropped.data_ptr(), int(bool(accumulate)), _stream(stream))
+    return hist, n_dropped
+
+
 def _render_desc(axis, mvp, width, height, base, grad, origin, weight, radius):
     r = _ffi.Render()
     for i in range(3):

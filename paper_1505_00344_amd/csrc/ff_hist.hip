@@ -236,6 +236,100 @@ hipError_t run_hist(const R* ax, const R* ay, int64_t n, const Geom& g, uint32_t
 }  // namespace
 
 namespace {
+
+// A validated projection request: the geometry and the two axis columns.
+struct Projection {
+    Geom g;
+    const void* ax;
+    const void* ay;
+    int64_t n;
+    bool f64;
+};
+
+ff_status check_projection(const ff_system_s* sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
+                           double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx, int32_t ny,
+                           const uint32_t* hist, Projection* out) {
+    if (ff_status s = check_system(sys)) return s;
+    if (ff_status s = check_batch(sys, b, false)) return s;
+    if (b->n > 0 && !b->state) return fail(FF_E_INVALID, "batch.state is NULL");
+    auto axis_ok = [&](int a) { return (a >= 0 && a < sys->dim) || (a < 0 && -1 - a < b->n_pp); };
+    if (!axis_ok(axis_x) || !axis_ok(axis_y))
+        return fail(FF_E_INVALID, "axis must be a state component (>= 0) or -1 - k for a per-particle parameter k");
+    if (nx <= 0 || ny <= 0) return fail(FF_E_INVALID, "nx and ny must be positive");
+    if ((int64_t)nx * ny > (int64_t)kMaxTiles * kTile) return fail(FF_E_UNSUPPORTED, "grid larger than 64M bins");
+    if (!std::isfinite(x_lo) || !std::isfinite(x_hi) || !std::isfinite(y_lo) || !std::isfinite(y_hi) ||
+        !(x_hi > x_lo) || !(y_hi > y_lo))
+        return fail(FF_E_INVALID, "ranges must be finite with hi > lo");
+    if (!hist) return fail(FF_E_INVALID, "hist is NULL");
+    if (b->n > 0x7fffffffLL) return fail(FF_E_UNSUPPORTED, "more than 2^31 - 1 particles in one projection");
+    Geom g;
+    g.xlo = x_lo;
+    g.ylo = y_lo;
+    g.sx = (double)nx / (x_hi - x_lo);
+    g.sy = (double)ny / (y_hi - y_lo);
+    if (!std::isfinite(g.sx) || !std::isfinite(g.sy)) return fail(FF_E_INVALID, "range too small");
+    g.nx = nx;
+    g.ny = ny;
+    const size_t esz = prec_size(b->prec);
+    auto col = [&](int a) -> const void* {
+        return a >= 0 ? (const char*)b->state + (size_t)a * b->ld * esz
+                      : (const char*)b->pparams + (size_t)(-1 - a) * b->ld * esz;
+    };
+    out->g = g;
+    out->ax = col(axis_x);
+    out->ay = col(axis_y);
+    out->n = b->n;
+    out->f64 = b->prec == FF_FP64;
+    return FF_OK;
+}
+
+hipError_t run_projection(const Projection& P, uint32_t* hist, unsigned long long* dropped, bool accumulate,
+                          char* ws, hipStream_t st) {
+    if (P.f64)
+        return run_hist<double>((const double*)P.ax, (const double*)P.ay, P.n, P.g, hist, dropped, accumulate, ws,
+                                st);
+    return run_hist<float>((const float*)P.ax, (const float*)P.ay, P.n, P.g, hist, dropped, accumulate, ws, st);
+}
+
+}  // namespace
+
+// Scratch of ff_project_histogram_noalloc: a file-scope device array, one
+// copy per GPU (at its own address), held from the library's load on that
+// GPU until the process ends.  Every buffer in it is written before it is
+// read within one call, so nothing needs clearing between calls.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in): the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocBytes = (size_t)FF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device (no allocation, now or later).
+ff_status noalloc_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_fail(e, "hipGetSymbolAddress of the histogram's static scratch");
+        if (!p) return fail(FF_E_DEVICE, "hipGetSymbolAddress returned a null address for the static scratch");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return FF_OK;
+}
+
+}  // namespace
+
+namespace {
 // Library-owned scratch per device and use (grown on demand, kept for the
 // process).
 struct Scratch {
@@ -298,30 +392,11 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
                                int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
                                void* workspace, size_t workspace_bytes, void* stream) {
     set_error("");
-    if (ff_status s = check_system(sys)) return s;
-    if (ff_status s = check_batch(sys, b, false)) return s;
-    if (b->n > 0 && !b->state) return fail(FF_E_INVALID, "batch.state is NULL");
-    auto axis_ok = [&](int a) { return (a >= 0 && a < sys->dim) || (a < 0 && -1 - a < b->n_pp); };
-    if (!axis_ok(axis_x) || !axis_ok(axis_y))
-        return fail(FF_E_INVALID, "axis must be a state component (>= 0) or -1 - k for a per-particle parameter k");
-    if (nx <= 0 || ny <= 0) return fail(FF_E_INVALID, "nx and ny must be positive");
-    if ((int64_t)nx * ny > (int64_t)kMaxTiles * kTile) return fail(FF_E_UNSUPPORTED, "grid larger than 64M bins");
-    if (!std::isfinite(x_lo) || !std::isfinite(x_hi) || !std::isfinite(y_lo) || !std::isfinite(y_hi) ||
-        !(x_hi > x_lo) || !(y_hi > y_lo))
-        return fail(FF_E_INVALID, "ranges must be finite with hi > lo");
-    if (!hist) return fail(FF_E_INVALID, "hist is NULL");
-    if (b->n > 0x7fffffffLL) return fail(FF_E_UNSUPPORTED, "more than 2^31 - 1 particles in one projection");
-    Geom g;
-    g.xlo = x_lo;
-    g.ylo = y_lo;
-    g.sx = (double)nx / (x_hi - x_lo);
-    g.sy = (double)ny / (y_hi - y_lo);
-    if (!std::isfinite(g.sx) || !std::isfinite(g.sy)) return fail(FF_E_INVALID, "range too small");
-    g.nx = nx;
-    g.ny = ny;
+    Projection P;
+    if (ff_status s = check_projection(sys, b, axis_x, axis_y, x_lo, x_hi, y_lo, y_hi, nx, ny, hist, &P))
+        return s;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t nbins = (int64_t)nx * ny;
-    const size_t need = layout(b->n, nbins).total;
+    const size_t need = layout(b->n, (int64_t)nx * ny).total;
     char* ws = nullptr;
     if (need > 0 && b->n > 0) {
         if (workspace) {
@@ -334,20 +409,33 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
             ws = (char*)p;
         }
     }
-    const size_t esz = prec_size(b->prec);
-    auto col = [&](int a) -> const char* {
-        return a >= 0 ? (const char*)b->state + (size_t)a * b->ld * esz
-                      : (const char*)b->pparams + (size_t)(-1 - a) * b->ld * esz;
-    };
-    unsigned long long* dr = (unsigned long long*)n_dropped;
-    hipError_t e;
-    if (b->prec == FF_FP64)
-        e = run_hist<double>((const double*)col(axis_x), (const double*)col(axis_y), b->n, g, hist, dr,
-                             accumulate != 0, ws, st);
-    else
-        e = run_hist<float>((const float*)col(axis_x), (const float*)col(axis_y), b->n, g, hist, dr,
-                            accumulate != 0, ws, st);
+    const hipError_t e = run_projection(P, hist, (unsigned long long*)n_dropped, accumulate != 0, ws, st);
     if (e != hipSuccess) return device_fail(e, "ff_project_histogram launch");
+    return FF_OK;
+}
+
+ff_status ff_project_histogram_noalloc(ff_system_t sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
+                                       double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
+                                       int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
+                                       void* stream) {
+    set_error("");
+    Projection P;
+    if (ff_status s = check_projection(sys, b, axis_x, axis_y, x_lo, x_hi, y_lo, y_hi, nx, ny, hist, &P))
+        return s;
+    const size_t need = layout(b->n, (int64_t)nx * ny).total;
+    char* ws = nullptr;
+    if (need > 0 && b->n > 0) {
+        if (need > kNoAllocBytes)
+            return fail(FF_E_NOMEM, "ff_project_histogram_noalloc: this projection needs " + std::to_string(need) +
+                                        " bytes of scratch, more than the " + std::to_string(kNoAllocBytes) +
+                                        " bytes its static buffer holds; use ff_project_histogram with a workspace");
+        void* p = nullptr;
+        if (ff_status s = noalloc_scratch(&p)) return s;
+        ws = (char*)p;
+    }
+    const hipError_t e = run_projection(P, hist, (unsigned long long*)n_dropped, accumulate != 0, ws,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "ff_project_histogram_noalloc launch");
     return FF_OK;
 }
 
