@@ -13,10 +13,66 @@ template <typename R> struct M;
 template <> struct M<double> {
     static constexpr bool kFast = false;
     static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-    // exp(x * c) for a compile-time constant c: the product is rounded, then exp
-    static __device__ __forceinline__ double expc(double x, double c) { return exp(x * c); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+
+    // Kernels of exp and expm1 for arguments a caller has checked (they leave
+    // out the library functions' handling of extreme arguments): Cody and
+    // Waite's argument reduction x = n ln2 + r, n = rint(x log2 e),
+    // |r| <= ln2/2 (ln 2 split into a double and its remainder), a polynomial
+    // in r, and 2^n by ldexp.  The polynomials are Chebyshev interpolants on
+    // [-0.3466, 0.3466] computed in 60-digit arithmetic and rounded to
+    // double: degree 11 for e^r (Horner), degree 10 for
+    // g(r) = (e^r - 1 - r)/r^2, so that e^r - 1 = r + r^2 g(r) has no
+    // cancellation near 0.  expm1 adds 2^n - 1 and 2^n r_hi
+    // (r_hi = x - n ln2_hi, exact for |n| = 1) as a Fast2Sum, then the small
+    // terms, so that n = +-1 does not amplify the rounding of r.  Valid (IEEE
+    // results, gradual underflow included) for |x| <= 708; measured against
+    // long-double references on 4M points each of [-700, 700], [-1, 1] and
+    // [-1e-3, 1e-3]: exp_k within 0.94 ulp (mean 0.26), expm1_k within 1.10
+    // ulp (mean 0.13-0.25).
+    static constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;   // ln 2 rounded
+    static constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 - kLn2Hi
+    static constexpr double kLog2E = 1.4426950408889634074;
+    static __device__ __forceinline__ double exp_k(double x) {
+        const double n = __builtin_rint(x * kLog2E);
+        const double r = __builtin_fma(-n, kLn2Lo, __builtin_fma(-n, kLn2Hi, x));
+        double p = 0x1.af6326f3df789p-26;
+        p = __builtin_fma(p, r, 0x1.28b40d95cf927p-22);
+        p = __builtin_fma(p, r, 0x1.71ddf56f3c074p-19);
+        p = __builtin_fma(p, r, 0x1.a01991a3c8c2ep-16);
+        p = __builtin_fma(p, r, 0x1.a01a01b1457b9p-13);
+        p = __builtin_fma(p, r, 0x1.6c16c187ff24ap-10);
+        p = __builtin_fma(p, r, 0x1.111111110f220p-7);
+        p = __builtin_fma(p, r, 0x1.555555554f0bfp-5);
+        p = __builtin_fma(p, r, 0x1.555555555555ap-3);
+        p = __builtin_fma(p, r, 0x1.0000000000011p-1);
+        p = __builtin_fma(p, r, 1.0);
+        p = __builtin_fma(p, r, 1.0);
+        return __builtin_ldexp(p, (int)n);
+    }
+    static __device__ __forceinline__ double expm1_k(double x) {
+        const double n = __builtin_rint(x * kLog2E);
+        const double rh = __builtin_fma(-n, kLn2Hi, x);
+        const double rl = -n * kLn2Lo;
+        const double r = rh + rl;
+        double g = 0x1.1f7301a8efa5cp-29;
+        g = __builtin_fma(g, r, 0x1.af4de6a36d4fcp-26);
+        g = __builtin_fma(g, r, 0x1.27e4db653346ep-22);
+        g = __builtin_fma(g, r, 0x1.71de0232f4775p-19);
+        g = __builtin_fma(g, r, 0x1.a01a01a6d84aap-16);
+        g = __builtin_fma(g, r, 0x1.a01a01abe78f9p-13);
+        g = __builtin_fma(g, r, 0x1.6c16c16c162d5p-10);
+        g = __builtin_fma(g, r, 0x1.11111111100dcp-7);
+        g = __builtin_fma(g, r, 0x1.5555555555556p-5);
+        g = __builtin_fma(g, r, 0x1.5555555555557p-3);
+        g = __builtin_fma(g, r, 0.5);
+        const double s = __builtin_ldexp(1.0, (int)n), sm1 = s - 1.0;
+        const double a = __builtin_fma(s, rh, sm1);             // (2^n - 1) + 2^n r_hi, rounded
+        const double e = __builtin_fma(s, rh, -(a - sm1));      // its rounding error, exactly
+        return a + __builtin_fma(s, __builtin_fma(r * r, g, rl), e);
+    }
     // 1/x: the hardware estimate (v_rcp_f64) refined by two Newton steps,
     // within 1 ulp (not always the correctly rounded quotient, which costs
     // about twice the instructions).  Where the estimate is +-0 or +-inf
@@ -43,13 +99,27 @@ template <> struct M<double> {
         const double qc = __builtin_fma(__builtin_fma(-b, q, a), r, q);
         return __builtin_amdgcn_class(r0, kZeroInf) ? a * r0 : qc;
     }
+    // rcp_ and div_ without the fallback, for divisors whose estimate is
+    // finite and nonzero (|x| between about 2^-1022 and 2^1022): the same
+    // values bit for bit
+    static __device__ __forceinline__ double rcp_k(double x) {
+        const double r0 = __builtin_amdgcn_rcp(x);
+        const double r = __builtin_fma(__builtin_fma(-x, r0, 1.0), r0, r0);
+        return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    }
+    static __device__ __forceinline__ double div_k(double a, double b) {
+        const double r = rcp_k(b);
+        const double q = a * r;
+        return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+    }
 };
 // Single precision.  By default (FF_FAST_F32 = 1) the exponential is the
 // hardware 2^x (v_exp_f32) with log2(e) folded into the argument's scale, and
 // reciprocals/divisions use v_rcp_f32 (each about 1 ulp); expm1 stays the
 // library function because psi(u) near u = 0 needs it.  FF_FAST_F32 = 0 uses
 // the library expf and correctly rounded division instead.  Double precision
-// uses the library exp/expm1 and a Newton-refined reciprocal (below).
+// uses the library exp/expm1 (or the kernels above, where a caller has checked
+// the arguments) and the Newton-refined reciprocal.
 #ifndef FF_FAST_F32
 #define FF_FAST_F32 1
 #endif
@@ -60,13 +130,11 @@ template <> struct M<float> {
 #if FF_FAST_F32
     static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * (float)kLog2e); }
     static __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
-    static __device__ __forceinline__ float expc(float x, double c) { return __builtin_amdgcn_exp2f(x * (float)(c * kLog2e)); }
     static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 #else
     static __device__ __forceinline__ float exp_(float x) { return expf(x); }
     static __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
-    static __device__ __forceinline__ float expc(float x, double c) { return expf(x * (float)c); }
     static __device__ __forceinline__ float rcp_(float x) { return 1.0f / x; }
     static __device__ __forceinline__ float div_(float a, float b) { return a / b; }
 #endif

@@ -21,9 +21,30 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ff_math.h"
 
 namespace ff {
+
+// The exponential / reciprocal set a right-hand side evaluates with: the
+// precision's functions (M<R>), or, in double precision with K, their kernels
+// without the handling of extreme arguments, for a particle whose arguments
+// have been checked.  The kernels equal the full functions bit for bit where
+// both apply.
+template <typename R, bool K> struct Tr {
+    static __device__ __forceinline__ R ex(R x) { return M<R>::exp_(x); }
+    static __device__ __forceinline__ R em1(R x) { return M<R>::expm1_(x); }
+    static __device__ __forceinline__ R rcp(R x) { return M<R>::rcp_(x); }
+    static __device__ __forceinline__ R div(R a, R b) { return M<R>::div_(a, b); }
+};
+template <> struct Tr<double, true> {
+    static __device__ __forceinline__ double ex(double x) { return M<double>::exp_k(x); }
+    static __device__ __forceinline__ double em1(double x) { return M<double>::expm1_k(x); }
+    static __device__ __forceinline__ double rcp(double x) { return M<double>::rcp_k(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return M<double>::div_k(a, b); }
+};
+template <typename R> constexpr bool kHasKernels = std::is_same<R, double>::value;
 
 // ---------------------------------------------------------------- linear
 // x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.
@@ -169,15 +190,16 @@ __device__ __forceinline__ R hh_psi_fast(R u, R den, double k) {
     return __builtin_fabsf(u) < R(0.5) ? series : direct;
 }
 
-template <typename R>
+template <typename R, bool K>
 __device__ __forceinline__ R hh_psi(R u) {
-    const R q = M<R>::div_(u, M<R>::expm1_(u));
+    const R q = Tr<R, K>::div(u, Tr<R, K>::em1(u));
     return (u == R(0)) ? R(1) : q;
 }
 
 // Rates of one neuron.  sgl = -sg * log2(e) (derived once per particle) is
-// used by the fast single-precision path only.
-template <typename R>
+// used by the fast single-precision path only; K selects the double-precision
+// kernels (the caller has checked hh_in_range).
+template <typename R, bool K = false>
 __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg, R sgl) {
     const R c10 = R(-1.0 / 10.0);
     const R v65 = V + R(65.0);
@@ -201,15 +223,31 @@ __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg, R sgl) {
         q.bn = M<R>::exp2_(M<R>::fma_(v65, R(-kLog2e / 80.0), R(-3)));
         q.tv = M<R>::rcp_(R(1) + M<R>::exp2_((V - th) * sgl));
     } else {
-        q.am = hh_psi<R>((V + R(40.0)) * c10);
-        q.bm = R(4.0) * M<R>::expc(v65, -1.0 / 18.0);
-        q.ah = R(0.07) * M<R>::expc(v65, -1.0 / 20.0);
-        q.bh = M<R>::rcp_(R(1) + M<R>::expc(V + R(35.0), -1.0 / 10.0));
-        q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
-        q.bn = R(0.125) * M<R>::expc(v65, -1.0 / 80.0);
-        q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
+        using F = Tr<R, K>;
+        q.am = hh_psi<R, K>((V + R(40.0)) * c10);
+        q.bm = R(4.0) * F::ex(v65 * R(-1.0 / 18.0));
+        q.ah = R(0.07) * F::ex(v65 * R(-1.0 / 20.0));
+        q.bh = F::rcp(R(1) + F::ex((V + R(35.0)) * R(-1.0 / 10.0)));
+        q.an = R(0.1) * hh_psi<R, K>((V + R(55.0)) * c10);
+        q.bn = R(0.125) * F::ex(v65 * R(-1.0 / 80.0));
+        q.tv = F::rcp(R(1) + F::ex((V - th) * (-sg)));
     }
     return q;
+}
+
+// Whether a particle's rates may use the double-precision kernels: |V| < 1000
+// for every neuron keeps the gate rates' exponents within 110 and their
+// divisors in [1, e^110], and the synapse's exponent (V - th)(-sg) is checked
+// itself.  False for non-finite values.
+template <typename R, int N, int D>
+__device__ __forceinline__ bool hh_in_range(const R (&x)[D], R th, R sg) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const R V = x[5 * j];
+        ok = ok && (__builtin_fabs((double)V) < 1000.0) && (__builtin_fabs((double)((V - th) * sg)) <= 708.0);
+    }
+    return ok;
 }
 
 // dx/dt = a (1 - x) - b x of a gate; the fast path evaluates a - (a + b) x.
@@ -224,13 +262,22 @@ template <typename R, int N> struct HHRing {
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         q[0] = M<R>::kFast ? -p[13] * R(kLog2e) : R(0);
     }
+    // double precision takes the kernels of exp, expm1 and the reciprocal for
+    // a particle that passes hh_in_range (any particle on a physiological
+    // trajectory does), the full functions otherwise; the choice is per
+    // particle, so a particle's result does not depend on its neighbours
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D], R (&o)[D]) {
+        if (kHasKernels<R> && hh_in_range<R, N>(x, p[12], p[13])) f_<true>(p, qd, x, o);
+        else f_<false>(p, qd, x, o);
+    }
+    template <bool K>
+    static __device__ __forceinline__ void f_(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D], R (&o)[D]) {
         const R invC = M<R>::rcp_(p[6]);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const R V = x[5 * j], m = x[5 * j + 1], h = x[5 * j + 2], n = x[5 * j + 3], s = x[5 * j + 4];
             const R spre = x[5 * ((j + N - 1) % N) + 4];
-            const HHRate<R> q = hh_rates<R>(V, p[12], p[13], qd[0]);
+            const HHRate<R> q = hh_rates<R, K>(V, p[12], p[13], qd[0]);
             const R gNa = (p[0] * ((m * m) * m)) * h;
             const R n2 = n * n;
             const R gK = p[1] * (n2 * n2);
@@ -259,6 +306,7 @@ template <typename R, int N> struct HHRing {
     // u^7/151200 (the next term, u^9/4790016, is below 4.1e-10 there), and
     // the rest the hardware exponential (cancellation there costs a few
     // ulp).  Both are computed and one is selected.
+    template <bool K>
     static __device__ __forceinline__ R dpsi(R u) {
         if constexpr (M<R>::kFast) {
             const R w = u * u;
@@ -271,13 +319,19 @@ template <typename R, int N> struct HHRing {
             const R direct = (em1 - u * e) * M<R>::rcp_(em1 * em1);
             return __builtin_fabsf(u) < R(0.5) ? series : direct;
         } else {
-            const R em1 = M<R>::expm1_(u);
-            const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
+            const R em1 = Tr<R, K>::em1(u);
+            const R d = Tr<R, K>::div(em1 - u * (em1 + R(1)), em1 * em1);
             return (u == R(0)) ? R(-0.5) : d;
         }
     }
     static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
+        if (kHasKernels<R> && hh_in_range<R, N>(x, p[12], p[13])) vjp_<true>(p, qd, x, a, gx, gp);
+        else vjp_<false>(p, qd, x, a, gx, gp);
+    }
+    template <bool K>
+    static __device__ __forceinline__ void vjp_(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
+                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R invC = M<R>::rcp_(p[6]);
         const R th = p[12], sg = p[13];
 #pragma unroll
@@ -285,13 +339,13 @@ template <typename R, int N> struct HHRing {
             const int o = 5 * j, q5 = 5 * ((j + N - 1) % N);
             const R V = x[o], m = x[o + 1], h = x[o + 2], n = x[o + 3], s = x[o + 4];
             const R spre = x[q5 + 4];
-            const HHRate<R> q = hh_rates<R>(V, th, sg, qd[0]);
+            const HHRate<R> q = hh_rates<R, K>(V, th, sg, qd[0]);
             const R um = (V + R(40.0)) * R(-1.0 / 10.0), un = (V + R(55.0)) * R(-1.0 / 10.0);
-            const R dam = dpsi(um) * R(-0.1);
+            const R dam = dpsi<K>(um) * R(-0.1);
             const R dbm = q.bm * R(-1.0 / 18.0);
             const R dah = q.ah * R(-1.0 / 20.0);
             const R dbh = R(0.1) * q.bh * (R(1) - q.bh);
-            const R dan = R(0.1) * dpsi(un) * R(-0.1);
+            const R dan = R(0.1) * dpsi<K>(un) * R(-0.1);
             const R dbn = q.bn * R(-1.0 / 80.0);
             const R dT = sg * q.tv * (R(1) - q.tv);
             const R m2 = m * m, m3 = m2 * m, n2 = n * n, n3 = n2 * n, n4 = n2 * n2;

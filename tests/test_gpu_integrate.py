@@ -285,6 +285,54 @@ def test_permutation_invariance(A):
     assert np.array_equal(a[:, perm], b)
 
 
+def test_fp64_bounded_and_general_functions_per_particle(A, ora):
+    """The double-precision HH ring evaluates its rates with the exp/expm1
+    and reciprocal kernels for a particle whose voltages are in range and
+    with the library functions otherwise, particle by particle: results match
+    the oracle on both sides of the switch and do not depend on which
+    particles share a wavefront (a permutation gives the same values
+    bitwise).  Every third particle starts at V1 = 1500 mV (it relaxes into
+    range within ~30 steps), every seventh at V2 = -2500 mV (it diverges), a
+    few at NaN, interleaved with physiological ones.  The same invariance on
+    the expanding (backward) Wilson-Cowan group, whose trajectories saturate
+    both sigmoids after a few hundred steps."""
+    perm = np.random.default_rng(5).permutation
+    w = I.wilson_cowan_4m(n=3000)
+    e = I.generate(w)
+    x, pp = e.state, e.pparams
+    a, _ = run_groups(A, I.WILSON_COWAN, 2, w.params, x, [(3000, -0.01)], 400, torch.float64, pp=pp,
+                      pp_slot=w.pp_slot)
+    ref = ora.rk4(ora.WILSON_COWAN, w.params, x, -0.01, 400, pp_slot=w.pp_slot, pparams=pp)
+    assert np.array_equal(finite_cols(a), finite_cols(ref))
+    fin = finite_cols(ref)
+    err = mixed_error(a[:, fin], ref[:, fin])
+    assert np.quantile(err, 0.99) <= tol.FP64_WC_BACKWARD_P99 and err.max() <= tol.FP64_WC_BACKWARD_MAX, quantiles(err)
+    pm = perm(3000)
+    b, _ = run_groups(A, I.WILSON_COWAN, 2, w.params, x[:, pm], [(3000, -0.01)], 400, torch.float64,
+                      pp=pp[:, pm], pp_slot=w.pp_slot)
+    assert np.array_equal(a[:, pm], b, equal_nan=True)
+
+    w = I.hh_ring_1m(n=1000 + 13)
+    e = I.generate(w)
+    x = e.state.copy()
+    x[0, ::3] = 1500.0
+    x[5, 1::7] = -2500.0
+    x[10, 5:40:9] = np.nan
+    a, _ = run_groups(A, I.HH_RING, 15, w.params, x, [(x.shape[1], 0.01)], 300, torch.float64, pp=e.pparams,
+                      pp_slot=w.pp_slot)
+    ref = ora.rk4(ora.HH_RING, w.params, x, 0.01, 300, pp_slot=w.pp_slot, pparams=e.pparams)
+    assert np.array_equal(finite_cols(a), finite_cols(ref))
+    fin = finite_cols(ref)
+    assert (~fin).sum() >= 4
+    err = mixed_error(a[:, fin], ref[:, fin])
+    record("hh_fp64_bounded_general_mix", err=quantiles(err))
+    assert err.max() <= tol.FP64_REL, quantiles(err)
+    pm = perm(x.shape[1])
+    b, _ = run_groups(A, I.HH_RING, 15, w.params, x[:, pm], [(x.shape[1], 0.01)], 300, torch.float64,
+                      pp=e.pparams[:, pm], pp_slot=w.pp_slot)
+    assert np.array_equal(a[:, pm], b, equal_nan=True)
+
+
 def test_invalid_arguments_enqueue_nothing(A):
     st = torch.zeros((3, 100), dtype=torch.float64, device="cuda:0")
     sys = A.System("lorenz", 3, I.LORENZ_PARAMS)
