@@ -14,12 +14,18 @@ RK4 kernel): algorithmic FLOPs per launch / its average duration from HIP
 events recorded on the stream it runs on.  `fp64` is the same workload in
 double precision, `adjoint` the adjoint particle-steps/s of the Lorenz
 bifurcation workload (8M particles, 200 steps, checkpoints every 50) with
-the reverse sweep's fraction of the VALU peak, and
-`cpu_baseline` times the CPU oracle (FP64, all host threads) on a bounded
-sample of the ensemble.  --extended adds the other workloads.
+the reverse sweep's fraction of the VALU peak, `workloads` the other
+configurations of the metric (Lorenz 8M bifurcation in FP32, FP32-Kahan and
+FP64; the HH ring 1M in FP32-Kahan and FP64 with its adjoint; the ragged mixed
+batch, persistent against per-group launches, and its captured frame's
+p50/p99), and `cpu_baseline` times the CPU oracle (FP64, all host threads) on
+a bounded sample of the ensemble.  --extended adds the reset rule, recording,
+the render technique, expression systems, the one-step-per-launch pattern,
+the paper's Table 1 single-step times and the Lorenz 8M adjoint in every
+precision.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
-                  [--no-adjoint] [--extended [--only WORKLOAD]]
+                  [--no-adjoint] [--no-workloads] [--extended [--only WORKLOAD]]
 """
 from __future__ import annotations
 
@@ -111,8 +117,11 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement (lorenz_8m)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the baseline (three timed runs of a third each)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other configurations (Lorenz 8M, HH ring 1M, mixed batch)")
     ap.add_argument("--extended", action="store_true",
-                    help="also measure the other workloads (Lorenz 8M, HH ring 1M, adjoints, mixed batch)")
+                    help="also measure the reset rule, recording, render technique, expression systems, the "
+                         "one-step-per-launch pattern, Table 1's single-step times and every Lorenz 8M adjoint")
     ap.add_argument("--only", default=None,
                     help="with --extended: measure only this workload (lorenz_8m, hh_ring_1m, mixed_batch, "
                          "reset_record_render_expressions, one_step_per_launch, table1_single_step)")
@@ -267,17 +276,19 @@ def main():
         out["fp32_kahan_vs_fp64"] = acc
         out["fp64_input_rounding"] = inp
         del A32, A64, A64o
+    del B
+    torch.cuda.empty_cache()
     if not args.no_adjoint:
-        del B
-        torch.cuda.empty_cache()
         out["adjoint"] = adjoint_line(A, I, torch)
+    if not args.no_workloads:
+        # the other configurations of the metric, measured in the same run
+        out["workloads"] = extended(A, I, torch, np, names=DEFAULT_WORKLOADS, lorenz_adjoint_all=False)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(e, w, args.cpu_seconds)
     if args.extended:
-        if args.no_adjoint:
-            del B
         torch.cuda.empty_cache()
-        out["extended"] = extended(A, I, torch, np, only=args.only)
+        names = EXTENDED_WORKLOADS if args.only is None else (args.only,)
+        out["extended"] = extended(A, I, torch, np, names=names)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -352,8 +363,14 @@ def adjoint_line(A, I, torch):
     return out
 
 
-def extended(A, I, torch, np, only=None):
-    """Throughput of the other workloads (each run once after a warm-up)."""
+DEFAULT_WORKLOADS = ("lorenz_8m", "hh_ring_1m", "mixed_batch")
+EXTENDED_WORKLOADS = ("lorenz_8m", "reset_record_render_expressions", "one_step_per_launch", "table1_single_step")
+
+
+def extended(A, I, torch, np, names, lorenz_adjoint_all=True):
+    """Throughput of the other workloads (each run after a warm-up).  The
+    Lorenz 8M adjoint is measured per precision only with
+    lorenz_adjoint_all (the headline line carries FP64 and FP32-Kahan)."""
     dev = torch.device("cuda:0")
     res = {}
 
@@ -374,7 +391,8 @@ def extended(A, I, torch, np, only=None):
             ps = w.n * w.nsteps / (ms * 1e-3)
             tf = ps * FLOP_PER_STEP["lorenz"][prec] / 1e12
             r[prec] = {"particle_steps_per_s": ps, "ms": ms, "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[prec]}
-            r[prec]["adjoint"] = lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec)
+            if lorenz_adjoint_all:
+                r[prec]["adjoint"] = lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec)
             del st, st0, pp, comp
         return r
 
@@ -654,7 +672,7 @@ def extended(A, I, torch, np, only=None):
     for name, fn in (("lorenz_8m", lorenz8m), ("hh_ring_1m", hh1m), ("mixed_batch", mixed),
                      ("reset_record_render_expressions", reset_record_render_expressions),
                      ("one_step_per_launch", one_step_per_launch), ("table1_single_step", table1_single_step)):
-        if only is not None and name != only:
+        if name not in names:
             continue
         try:
             res[name] = fn()
