@@ -304,7 +304,9 @@ ff_status ff_project_histogram(ff_system_t sys, const ff_batch* b, int32_t axis_
  * FF_E_NOMEM before anything is enqueued.  Every call on one GPU shares that
  * array: calls that overlap on one device (different streams, host threads)
  * race and must be ordered by the caller.  Nothing in it needs to start at
- * zero.  The first call on a device looks the array's address up there. */
+ * zero.  The first call on a device looks the array's address up there
+ * (hipGetSymbolAddress, which loads the library's code object on that device
+ * if nothing has yet): make that first call outside stream capture. */
 ff_status ff_project_histogram_noalloc(ff_system_t sys, const ff_batch* b, int32_t axis_x, int32_t axis_y,
                                        double x_lo, double x_hi, double y_lo, double y_hi, int32_t nx,
                                        int32_t ny, uint32_t* hist, uint64_t* n_dropped, int32_t accumulate,
