@@ -148,6 +148,20 @@ def test_histogram_and_adjoint_validation(L):
         st = L.ff_project_histogram(s.handle, ctypes.byref(b), ax, ay, lo, hi, 0.0, 1.0, nx, 8, 4096, None, 0,
                                     None, 0, None)
         assert st == _ffi.FF_E_INVALID
+    # the allocation-free projection validates the same way, refuses a NULL grid, and refuses a projection
+    # whose scratch would exceed its static buffer before touching a device
+    for ax, ay, lo, hi, nx in bad:
+        st = L.ff_project_histogram_noalloc(s.handle, ctypes.byref(b), ax, ay, lo, hi, 0.0, 1.0, nx, 8, 4096, None,
+                                            0, None)
+        assert st == _ffi.FF_E_INVALID
+    assert L.ff_project_histogram_noalloc(s.handle, ctypes.byref(b), 0, 1, 0.0, 1.0, 0.0, 1.0, 8, 8, None, None, 0,
+                                          None) == _ffi.FF_E_INVALID
+    n = 12 * 1024 * 1024
+    big = _batch(n=n, ld=n)
+    assert L.ff_histogram_workspace_size(n, 1024, 1024, ctypes.byref(sz)) == 0 and sz.value > 64 * 1024 * 1024
+    st = L.ff_project_histogram_noalloc(s.handle, ctypes.byref(big), 0, 2, -20.0, 20.0, 0.0, 50.0, 1024, 1024, 4096,
+                                        None, 0, None)
+    assert st == _ffi.FF_E_NOMEM and b"static" in L.ff_last_error()
     assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b), 200, 50, ctypes.byref(sz)) == 0
     # 4 checkpoints + 7 sub-checkpoints of 3 x 10 doubles, + partial sums
     assert sz.value >= (4 + 7) * 3 * 10 * 8

@@ -109,3 +109,46 @@ def test_noalloc_refuses_projection_beyond_its_scratch(A):
     assert ei.value.status == _ffi.FF_E_NOMEM and "static" in str(ei.value)
     torch.cuda.synchronize()
     assert bool((hist == 3).all()) and int(dropped.item()) == 5  # nothing was enqueued
+
+
+def test_noalloc_empty_batch_and_largest_accepted_size(A, ora):
+    from paper_1505_00344_amd import _ffi
+    w = I.wilson_cowan_4m()
+    sysobj = A.System("wilson_cowan", 2, w.params)
+    # an empty batch clears the grid and the drop count and touches nothing else
+    st = torch.zeros((2, 0), dtype=torch.float32, device="cuda:0")
+    pp = torch.zeros((1, 0), dtype=torch.float32, device="cuda:0")
+    hist = torch.full((1024, 1024), 9, dtype=torch.int32, device="cuda:0")
+    dropped = torch.full((1,), 9, dtype=torch.int64, device="cuda:0")
+    A.project_histogram_noalloc(sysobj, st, -1, 0, (-2.0, 4.0), (0.0, 1.0), 1024, 1024, hist=hist,
+                                n_dropped=dropped, pparams=pp, pp_slot=[8])
+    torch.cuda.synchronize()
+    assert bool((hist == 0).all()) and int(dropped.item()) == 0
+    # the largest particle count whose workspace fits the static buffer (on the
+    # 1024 x 1024 grid) is accepted and equals the workspace call; one more
+    # count block is refused
+    limit = 64 * 1024 * 1024
+
+    def need(n):
+        out = ctypes.c_size_t()
+        _ffi.call("ff_histogram_workspace_size", n, 1024, 1024, ctypes.byref(out))
+        return out.value
+
+    lo, hi = 1, 16 * 1024 * 1024
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if need(mid) <= limit else (lo, mid)
+    n_max = lo
+    assert need(n_max) <= limit < need(n_max + 1)
+    st, p = positions(n_max, 6)
+    dst, dpp = to_dev(st, torch.float32), to_dev(p, torch.float32)
+    (h, d), (r, e) = both(A, sysobj, dst, dpp, 1024, 1024, (-2.0, 4.0), (0.0, 1.0))
+    assert d == e and np.array_equal(h, r)
+    assert int(h.sum(dtype=np.int64)) + d == n_max
+    del dst, dpp
+    big = torch.zeros((2, n_max + 4096), dtype=torch.float32, device="cuda:0")
+    bigp = torch.zeros((1, n_max + 4096), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(_ffi.FirefliesError) as ei:
+        A.project_histogram_noalloc(sysobj, big, -1, 0, (-2.0, 4.0), (0.0, 1.0), 1024, 1024, pparams=bigp,
+                                    pp_slot=[8])
+    assert ei.value.status == _ffi.FF_E_NOMEM
