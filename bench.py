@@ -18,11 +18,11 @@ the reverse sweep's fraction of the VALU peak, `workloads` the other
 configurations of the metric (Lorenz 8M bifurcation in FP32, FP32-Kahan and
 FP64; the HH ring 1M in FP32-Kahan and FP64 with its adjoint; the ragged mixed
 batch, persistent against per-group launches, and its captured frame's
-p50/p99), and `cpu_baseline` times the CPU oracle (FP64, all host threads) on
-a bounded sample of the ensemble.  --extended adds the reset rule, recording,
-the render technique, expression systems, the one-step-per-launch pattern,
-the paper's Table 1 single-step times and the Lorenz 8M adjoint in every
-precision.
+p50/p99) and of the rest of the path (the reset rule, recording, the render
+technique, expression systems, the one-step-per-launch pattern, the paper's
+Table 1 single-step times), and `cpu_baseline` times the CPU oracle (FP64,
+all host threads) on a bounded sample of the ensemble.  --extended adds the
+Lorenz 8M adjoint in every precision (with --only: one workload alone).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
                   [--no-adjoint] [--no-workloads] [--extended [--only WORKLOAD]]
@@ -118,10 +118,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the baseline (three timed runs of a third each)")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the other configurations (Lorenz 8M, HH ring 1M, mixed batch)")
+                    help="skip the other configurations and parts of the path (the `workloads` object)")
     ap.add_argument("--extended", action="store_true",
-                    help="also measure the reset rule, recording, render technique, expression systems, the "
-                         "one-step-per-launch pattern, Table 1's single-step times and every Lorenz 8M adjoint")
+                    help="also measure the Lorenz 8M adjoint in every precision, with the reset rule, recording, "
+                         "render technique, expression systems, one step per launch and Table 1 again")
     ap.add_argument("--only", default=None,
                     help="with --extended: measure only this workload (lorenz_8m, hh_ring_1m, mixed_batch, "
                          "reset_record_render_expressions, one_step_per_launch, table1_single_step)")
@@ -363,7 +363,8 @@ def adjoint_line(A, I, torch):
     return out
 
 
-DEFAULT_WORKLOADS = ("lorenz_8m", "hh_ring_1m", "mixed_batch")
+DEFAULT_WORKLOADS = ("lorenz_8m", "hh_ring_1m", "mixed_batch", "reset_record_render_expressions",
+                     "one_step_per_launch", "table1_single_step")
 EXTENDED_WORKLOADS = ("lorenz_8m", "reset_record_render_expressions", "one_step_per_launch", "table1_single_step")
 
 
