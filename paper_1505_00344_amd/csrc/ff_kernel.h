@@ -305,14 +305,8 @@ __device__ __forceinline__ void rk4_tile(const RK4Args& a, int64_t first, const 
     }
 }
 
-// Waves per SIMD that the fused kernel of system S with PPT particles per
-// thread must fit, i.e. a register cap (1: none); specialised where measured.
-template <class S, int PPT> struct RK4MinWaves {
-    static constexpr int value = 1;
-};
-
 template <class S, typename R, bool KAHAN, int PPT>
-__global__ void __launch_bounds__(256, (RK4MinWaves<S, PPT>::value)) k_rk4(RK4Args a) {
+__global__ void __launch_bounds__(256) k_rk4(RK4Args a) {
     rk4_tile<S, R, KAHAN, PPT>(a, (int64_t)blockIdx.x * ((int64_t)blockDim.x * PPT));
 }
 

@@ -27,23 +27,29 @@
 
 namespace ff {
 
-// The exponential / reciprocal set a right-hand side evaluates with: the
-// precision's functions (M<R>), or, in double precision with K, their kernels
-// without the handling of extreme arguments, for a particle whose arguments
-// have been checked.  The kernels equal the full functions bit for bit where
-// both apply.
-template <typename R, bool K> struct Tr {
-    static __device__ __forceinline__ R ex(R x) { return M<R>::exp_(x); }
-    static __device__ __forceinline__ R em1(R x) { return M<R>::expm1_(x); }
-    static __device__ __forceinline__ R rcp(R x) { return M<R>::rcp_(x); }
-    static __device__ __forceinline__ R div(R a, R b) { return M<R>::div_(a, b); }
-};
-template <> struct Tr<double, true> {
-    static __device__ __forceinline__ double ex(double x) { return M<double>::exp_k(x); }
-    static __device__ __forceinline__ double em1(double x) { return M<double>::expm1_k(x); }
-    static __device__ __forceinline__ double rcp(double x) { return M<double>::rcp_k(x); }
-    static __device__ __forceinline__ double div(double a, double b) { return M<double>::div_k(a, b); }
-};
+// Double precision evaluates the exponentials and reciprocals of the built-in
+// right-hand sides with the kernels of M<double> (no branches, so no result
+// depends on the other particles of a wave).  Their arguments are clamped
+// where the function is flat anyway, so that the kernels never see an
+// argument outside their range on any trajectory, however far it escapes.
+
+// 1/(1 + e^z) from the exp and reciprocal kernels.  z is clamped to
+// [-700, 700] first: beyond it the logistic is 0 or 1 to within 1e-304
+// (e^-700 = 9.9e-305), and inside it 1 + e^z is finite and its reciprocal
+// normal, so the kernels need no fallback.  With KEEP_NAN the bounds are
+// formed as fma(0, z, -+700), which is NaN exactly when z is NaN or infinite,
+// so that a NaN argument stays NaN through the clamp (an infinite z, from an
+// infinite state or one within a factor ~16 of overflow, then gives NaN
+// instead of 0 or 1); without it a NaN z gives a finite result, for callers
+// whose NaN z implies a NaN state component anyway.
+template <bool KEEP_NAN>
+__device__ __forceinline__ double logistic_k(double z) {
+    const double lo = KEEP_NAN ? __builtin_fma(0.0, z, -700.0) : -700.0;
+    const double hi = KEEP_NAN ? __builtin_fma(0.0, z, 700.0) : 700.0;
+    const double zc = __builtin_fmin(__builtin_fmax(z, lo), hi);
+    return M<double>::rcp_k(1.0 + M<double>::exp_k(zc));
+}
+
 template <typename R> constexpr bool kHasKernels = std::is_same<R, double>::value;
 
 // ---------------------------------------------------------------- linear
@@ -127,8 +133,14 @@ template <typename R> struct WilsonCowan {
         } else {
             const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
             const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-            sE = M<R>::rcp_(R(1) + M<R>::exp_(-(p[4] * (uE - p[5]))));
-            sI = M<R>::rcp_(R(1) + M<R>::exp_(-(p[6] * (uI - p[7]))));
+            if constexpr (kHasKernels<R>) {
+                // a NaN per-particle P must reach the state through S_E
+                sE = logistic_k<true>(-(p[4] * (uE - p[5])));
+                sI = logistic_k<true>(-(p[6] * (uI - p[7])));
+            } else {
+                sE = M<R>::rcp_(R(1) + M<R>::exp_(-(p[4] * (uE - p[5]))));
+                sI = M<R>::rcp_(R(1) + M<R>::exp_(-(p[6] * (uI - p[7]))));
+            }
         }
     }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R (&o)[D]) {
@@ -190,16 +202,22 @@ __device__ __forceinline__ R hh_psi_fast(R u, R den, double k) {
     return __builtin_fabsf(u) < R(0.5) ? series : direct;
 }
 
-template <typename R, bool K>
+template <typename R>
 __device__ __forceinline__ R hh_psi(R u) {
-    const R q = Tr<R, K>::div(u, Tr<R, K>::em1(u));
-    return (u == R(0)) ? R(1) : q;
+    if constexpr (kHasKernels<R>) {
+        // u > 700 (V < -7040 mV): psi is below 1e-301 and e^u would overflow
+        // (a NaN u gives a NaN quotient through the numerator)
+        const R q = M<double>::div_k(u, M<double>::expm1_k(__builtin_fmin(u, 700.0)));
+        return (u == R(0)) ? R(1) : q;
+    } else {
+        const R q = M<R>::div_(u, M<R>::expm1_(u));
+        return (u == R(0)) ? R(1) : q;
+    }
 }
 
 // Rates of one neuron.  sgl = -sg * log2(e) (derived once per particle) is
-// used by the fast single-precision path only; K selects the double-precision
-// kernels (the caller has checked hh_in_range).
-template <typename R, bool K = false>
+// used by the fast single-precision path only.
+template <typename R>
 __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg, R sgl) {
     const R c10 = R(-1.0 / 10.0);
     const R v65 = V + R(65.0);
@@ -223,31 +241,27 @@ __device__ __forceinline__ HHRate<R> hh_rates(R V, R th, R sg, R sgl) {
         q.bn = M<R>::exp2_(M<R>::fma_(v65, R(-kLog2e / 80.0), R(-3)));
         q.tv = M<R>::rcp_(R(1) + M<R>::exp2_((V - th) * sgl));
     } else {
-        using F = Tr<R, K>;
-        q.am = hh_psi<R, K>((V + R(40.0)) * c10);
-        q.bm = R(4.0) * F::ex(v65 * R(-1.0 / 18.0));
-        q.ah = R(0.07) * F::ex(v65 * R(-1.0 / 20.0));
-        q.bh = F::rcp(R(1) + F::ex((V + R(35.0)) * R(-1.0 / 10.0)));
-        q.an = R(0.1) * hh_psi<R, K>((V + R(55.0)) * c10);
-        q.bn = R(0.125) * F::ex(v65 * R(-1.0 / 80.0));
-        q.tv = F::rcp(R(1) + F::ex((V - th) * (-sg)));
+        q.am = hh_psi<R>((V + R(40.0)) * c10);
+        q.an = R(0.1) * hh_psi<R>((V + R(55.0)) * c10);
+        if constexpr (kHasKernels<R>) {
+            // the exp kernel overflows to inf and underflows to 0 like the
+            // library function for |x| <= 1e15 (|V| <= 1.8e16 mV)
+            q.bm = R(4.0) * M<double>::exp_k(v65 * R(-1.0 / 18.0));
+            q.ah = R(0.07) * M<double>::exp_k(v65 * R(-1.0 / 20.0));
+            // a NaN V makes V' NaN by itself; the synapse's argument also
+            // carries the parameters th and sg, whose NaN must propagate
+            q.bh = logistic_k<false>((V + R(35.0)) * R(-1.0 / 10.0));
+            q.bn = R(0.125) * M<double>::exp_k(v65 * R(-1.0 / 80.0));
+            q.tv = logistic_k<true>((V - th) * (-sg));
+        } else {
+            q.bm = R(4.0) * M<R>::exp_(v65 * R(-1.0 / 18.0));
+            q.ah = R(0.07) * M<R>::exp_(v65 * R(-1.0 / 20.0));
+            q.bh = M<R>::rcp_(R(1) + M<R>::exp_((V + R(35.0)) * R(-1.0 / 10.0)));
+            q.bn = R(0.125) * M<R>::exp_(v65 * R(-1.0 / 80.0));
+            q.tv = M<R>::rcp_(R(1) + M<R>::exp_((V - th) * (-sg)));
+        }
     }
     return q;
-}
-
-// Whether a particle's rates may use the double-precision kernels: |V| < 1000
-// for every neuron keeps the gate rates' exponents within 110 and their
-// divisors in [1, e^110], and the synapse's exponent (V - th)(-sg) is checked
-// itself.  False for non-finite values.
-template <typename R, int N, int D>
-__device__ __forceinline__ bool hh_in_range(const R (&x)[D], R th, R sg) {
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const R V = x[5 * j];
-        ok = ok && (__builtin_fabs((double)V) < 1000.0) && (__builtin_fabs((double)((V - th) * sg)) <= 708.0);
-    }
-    return ok;
 }
 
 // dx/dt = a (1 - x) - b x of a gate; the fast path evaluates a - (a + b) x.
@@ -262,22 +276,13 @@ template <typename R, int N> struct HHRing {
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         q[0] = M<R>::kFast ? -p[13] * R(kLog2e) : R(0);
     }
-    // double precision takes the kernels of exp, expm1 and the reciprocal for
-    // a particle that passes hh_in_range (any particle on a physiological
-    // trajectory does), the full functions otherwise; the choice is per
-    // particle, so a particle's result does not depend on its neighbours
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D], R (&o)[D]) {
-        if (kHasKernels<R> && hh_in_range<R, N>(x, p[12], p[13])) f_<true>(p, qd, x, o);
-        else f_<false>(p, qd, x, o);
-    }
-    template <bool K>
-    static __device__ __forceinline__ void f_(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D], R (&o)[D]) {
         const R invC = M<R>::rcp_(p[6]);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const R V = x[5 * j], m = x[5 * j + 1], h = x[5 * j + 2], n = x[5 * j + 3], s = x[5 * j + 4];
             const R spre = x[5 * ((j + N - 1) % N) + 4];
-            const HHRate<R> q = hh_rates<R, K>(V, p[12], p[13], qd[0]);
+            const HHRate<R> q = hh_rates<R>(V, p[12], p[13], qd[0]);
             const R gNa = (p[0] * ((m * m) * m)) * h;
             const R n2 = n * n;
             const R gK = p[1] * (n2 * n2);
@@ -306,7 +311,6 @@ template <typename R, int N> struct HHRing {
     // u^7/151200 (the next term, u^9/4790016, is below 4.1e-10 there), and
     // the rest the hardware exponential (cancellation there costs a few
     // ulp).  Both are computed and one is selected.
-    template <bool K>
     static __device__ __forceinline__ R dpsi(R u) {
         if constexpr (M<R>::kFast) {
             const R w = u * u;
@@ -318,20 +322,21 @@ template <typename R, int N> struct HHRing {
             const R em1 = e - R(1);
             const R direct = (em1 - u * e) * M<R>::rcp_(em1 * em1);
             return __builtin_fabsf(u) < R(0.5) ? series : direct;
+        } else if constexpr (kHasKernels<R>) {
+            // u > 350 (V < -3540 mV): psi' is below 1e-149 and expm1(u)^2 would
+            // overflow (a NaN u: the state's V is NaN already)
+            const R uc = __builtin_fmin(u, 350.0);
+            const R em1 = M<double>::expm1_k(uc);
+            const R d = M<double>::div_k(em1 - uc * (em1 + R(1)), em1 * em1);
+            return (u == R(0)) ? R(-0.5) : d;
         } else {
-            const R em1 = Tr<R, K>::em1(u);
-            const R d = Tr<R, K>::div(em1 - u * (em1 + R(1)), em1 * em1);
+            const R em1 = M<R>::expm1_(u);
+            const R d = M<R>::div_(em1 - u * (em1 + R(1)), em1 * em1);
             return (u == R(0)) ? R(-0.5) : d;
         }
     }
     static __device__ __forceinline__ void vjp(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
-        if (kHasKernels<R> && hh_in_range<R, N>(x, p[12], p[13])) vjp_<true>(p, qd, x, a, gx, gp);
-        else vjp_<false>(p, qd, x, a, gx, gp);
-    }
-    template <bool K>
-    static __device__ __forceinline__ void vjp_(const R (&p)[NP], const R (&qd)[NQ], const R (&x)[D],
-                                                const R (&a)[D], R (&gx)[D], R (&gp)[NP]) {
         const R invC = M<R>::rcp_(p[6]);
         const R th = p[12], sg = p[13];
 #pragma unroll
@@ -339,13 +344,13 @@ template <typename R, int N> struct HHRing {
             const int o = 5 * j, q5 = 5 * ((j + N - 1) % N);
             const R V = x[o], m = x[o + 1], h = x[o + 2], n = x[o + 3], s = x[o + 4];
             const R spre = x[q5 + 4];
-            const HHRate<R> q = hh_rates<R, K>(V, th, sg, qd[0]);
+            const HHRate<R> q = hh_rates<R>(V, th, sg, qd[0]);
             const R um = (V + R(40.0)) * R(-1.0 / 10.0), un = (V + R(55.0)) * R(-1.0 / 10.0);
-            const R dam = dpsi<K>(um) * R(-0.1);
+            const R dam = dpsi(um) * R(-0.1);
             const R dbm = q.bm * R(-1.0 / 18.0);
             const R dah = q.ah * R(-1.0 / 20.0);
             const R dbh = R(0.1) * q.bh * (R(1) - q.bh);
-            const R dan = R(0.1) * dpsi<K>(un) * R(-0.1);
+            const R dan = R(0.1) * dpsi(un) * R(-0.1);
             const R dbn = q.bn * R(-1.0 / 80.0);
             const R dT = sg * q.tv * (R(1) - q.tv);
             const R m2 = m * m, m3 = m2 * m, n2 = n * n, n3 = n2 * n, n4 = n2 * n2;

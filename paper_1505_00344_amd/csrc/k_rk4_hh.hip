@@ -8,14 +8,6 @@ namespace ff {
 template <typename R> using HH1 = HHRing<R, 1>;
 template <typename R> using HH3 = HHRing<R, 3>;
 
-// The double-precision step (with both the exp/expm1 kernels and the library
-// functions for particles out of their range) takes 270 VGPRs, one wave per
-// SIMD; capped at 256 (two waves, 14 registers spilled) the three-neuron ring's
-// 1M particles x 2000 steps took 167 instead of 191 ms.
-template <int N> struct RK4MinWaves<HHRing<double, N>, 1> {
-    static constexpr int value = 2;
-};
-
 hipError_t launch_rk4_hh(int neurons, const RK4Launch& L) {
     switch (neurons) {
         case 1: return dispatch_rk4<HH1, 2>(L);

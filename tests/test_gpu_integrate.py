@@ -285,17 +285,17 @@ def test_permutation_invariance(A):
     assert np.array_equal(a[:, perm], b)
 
 
-def test_fp64_bounded_and_general_functions_per_particle(A, ora):
-    """The double-precision HH ring evaluates its rates with the exp/expm1
-    and reciprocal kernels for a particle whose voltages are in range and
-    with the library functions otherwise, particle by particle: results match
-    the oracle on both sides of the switch and do not depend on which
-    particles share a wavefront (a permutation gives the same values
-    bitwise).  Every third particle starts at V1 = 1500 mV (it relaxes into
-    range within ~30 steps), every seventh at V2 = -2500 mV (it diverges), a
-    few at NaN, interleaved with physiological ones.  The same invariance on
-    the expanding (backward) Wilson-Cowan group, whose trajectories saturate
-    both sigmoids after a few hundred steps."""
+def test_fp64_kernels_far_outside_the_physiological_range(A, ora):
+    """Double precision evaluates the rates and sigmoids with the project's
+    exp/expm1 and reciprocal kernels on clamped arguments: results match the
+    oracle (and its library functions) also on trajectories far outside the
+    physiological or unit-square range, the non-finite ones stay non-finite,
+    and nothing depends on which particles share a wavefront (a permutation
+    gives the same values bitwise).  HH ring: every third particle starts at
+    V1 = 1500 mV (it relaxes back within ~30 steps), every seventh at
+    V2 = -2500 mV (it diverges), a few at NaN, interleaved with physiological
+    ones.  Wilson-Cowan: the expanding (backward) group, whose trajectories
+    drive both sigmoids' exponents far past the clamp."""
     perm = np.random.default_rng(5).permutation
     w = I.wilson_cowan_4m(n=3000)
     e = I.generate(w)
@@ -325,7 +325,7 @@ def test_fp64_bounded_and_general_functions_per_particle(A, ora):
     fin = finite_cols(ref)
     assert (~fin).sum() >= 4
     err = mixed_error(a[:, fin], ref[:, fin])
-    record("hh_fp64_bounded_general_mix", err=quantiles(err))
+    record("hh_fp64_outside_range_mix", err=quantiles(err))
     assert err.max() <= tol.FP64_REL, quantiles(err)
     pm = perm(x.shape[1])
     b, _ = run_groups(A, I.HH_RING, 15, w.params, x[:, pm], [(x.shape[1], 0.01)], 300, torch.float64,
