@@ -373,7 +373,7 @@ std::string expr_struct(const ExprProgram& P, int prec) {
     std::string src = "namespace ffx {\n\nstruct Sys {\n";
     src += std::string("    using R = ") + R + ";\n";
     src += "    static constexpr int D = " + std::to_string(P.dim) + ", NP = " + std::to_string(P.np > 0 ? P.np : 1) +
-           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ";\n";
+           ", NQ = " + std::to_string(nq > 0 ? nq : 1) + ", UNROLL = " + (P.dim <= 4 ? "2" : "1") + ", FUSED_INC = 0;\n";
     src += "    static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {\n        (void)p;\n";
     if (nq == 0) src += "        q[0] = R(0);\n";
     for (size_t i = 0; i < N.size(); ++i) {

@@ -20,7 +20,10 @@
 //   k = f(y) [k3]; y = fma(h,k,x); acc = acc + k; acc = fma(2,acc,k1);
 //   k = f(y) [k4]; acc = acc + k; update.
 // Kahan-compensated update (single precision): inc = h6*acc; y = inc - c;
-// t = x + y; c = (t - x) - y; x = t.
+// t = x + y; c = (t - x) - y; x = t.  Systems with FUSED_INC (those evaluated
+// with the fast single-precision functions) form y = fma(h6, acc, -c) instead:
+// one instruction fewer per component, and the product's rounding, which the
+// compensation would otherwise not see, is left out.
 #pragma once
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
@@ -67,8 +70,7 @@ __device__ __forceinline__ void rk4_step(const R (&p)[S::NP], const R (&q)[S::NQ
     for (int d = 0; d < D; ++d) {
         acc[d] = acc[d] + k[d];
         if constexpr (KAHAN) {
-            const R inc = h6 * acc[d];
-            const R yk = inc - c[d];
+            const R yk = S::FUSED_INC ? M<R>::fma_(h6, acc[d], -c[d]) : h6 * acc[d] - c[d];
             const R t = x[d] + yk;
             c[d] = (t - x[d]) - yk;
             x[d] = t;

@@ -4,6 +4,9 @@
 // Each system is a struct template over the working precision R with
 //   D   number of state components,  NP  number of parameters,
 //   UNROLL  RK4 steps per trip of the fused kernel's step loop,
+//   FUSED_INC  nonzero: the compensated update forms inc - c as one fma
+//           (systems evaluated with the fast single-precision functions,
+//           which leave the canonical order anyway),
 //   NQ  number of constants derived from the parameters once per particle,
 //   derive(p, q)                 fill q from p,
 //   f(p, q, x, out)              the right-hand side (autonomous: no t),
@@ -55,7 +58,7 @@ template <typename R> constexpr bool kHasKernels = std::is_same<R, double>::valu
 // ---------------------------------------------------------------- linear
 // x' = A x with A row-major in p (Dm <= 4); the acc starts with column 0.
 template <typename R, int Dm> struct Linear {
-    static constexpr int D = Dm, NP = Dm * Dm, NQ = 1, UNROLL = 2;
+    static constexpr int D = Dm, NP = Dm * Dm, NQ = 1, UNROLL = 2, FUSED_INC = 0;
     static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
 #pragma unroll
@@ -81,7 +84,7 @@ template <typename R, int Dm> struct Linear {
 // ---------------------------------------------------------------- Lorenz
 // Section 2.2: x' = s (y - x), y' = x (r - z) - y, z' = x y - b z; p = [s, r, b].
 template <typename R> struct Lorenz {
-    static constexpr int D = 3, NP = 3, NQ = 1, UNROLL = 2;
+    static constexpr int D = 3, NP = 3, NQ = 1, UNROLL = 2, FUSED_INC = 0;
     static __device__ __forceinline__ void derive(const R (&)[NP], R (&q)[NQ]) { q[0] = R(0); }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&)[NQ], const R (&x)[D], R (&o)[D]) {
         o[0] = p[0] * (x[1] - x[0]);
@@ -112,7 +115,7 @@ template <typename R> struct WilsonCowan {
     // round the same number of times as the canonical order, with errors of
     // the same size.)  Otherwise the canonical order below is kept.
     static constexpr bool kFold = M<R>::kFast;
-    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1;
+    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1, FUSED_INC = kFold;
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         if constexpr (kFold) {
             const R gE = -p[4] * R(kLog2e), gI = -p[6] * R(kLog2e);
@@ -272,7 +275,7 @@ __device__ __forceinline__ R hh_gate(R a, R b, R x) {
 }
 
 template <typename R, int N> struct HHRing {
-    static constexpr int D = 5 * N, NP = 14, NQ = 1, UNROLL = 1;
+    static constexpr int D = 5 * N, NP = 14, NQ = 1, UNROLL = 1, FUSED_INC = M<R>::kFast;
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         q[0] = M<R>::kFast ? -p[13] * R(kLog2e) : R(0);
     }
