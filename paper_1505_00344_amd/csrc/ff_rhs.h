@@ -15,8 +15,11 @@
 // per-particle overrides already applied).
 //
 // Evaluation order is fixed (explicit fma(), compiled with
-// -ffp-contract=off) so that FP64 runs reproduce a CPU evaluation of the same
-// formulas operation for operation:
+// -ffp-contract=off).  The canonical orders below are the ones a CPU
+// evaluation of the formulas follows; Lorenz and linear FP64 runs reproduce
+// it operation for operation, HH FP64 keeps its order with the exp/expm1
+// kernels of M<double>, and the Wilson-Cowan sigmoids fold their gain in
+// double and fast single precision (WilsonCowan below):
 //   Lorenz:  fx = s*(y - x); fy = fma(x, r - z, -y); fz = fma(x, y, -(b*z))
 //   WC:      u = fma(c1, E, fma(-c2, I, P)); S = 1/(1 + exp(-(a*(u - th))))
 //   HH:      rates with multiplications by the doubles nearest -1/10, -1/18,
@@ -39,18 +42,27 @@ namespace ff {
 // 1/(1 + e^z) from the exp and reciprocal kernels.  z is clamped to
 // [-700, 700] first: beyond it the logistic is 0 or 1 to within 1e-304
 // (e^-700 = 9.9e-305), and inside it 1 + e^z is finite and its reciprocal
-// normal, so the kernels need no fallback.  With KEEP_NAN the bounds are
-// formed as fma(0, z, -+700), which is NaN exactly when z is NaN or infinite,
-// so that a NaN argument stays NaN through the clamp (an infinite z, from an
+// normal, so the kernels need no fallback.  The clamp (IEEE max and min)
+// turns a NaN argument into a bound; with KEEP_NAN the result is
+// fma(0, z, S), which is S for every finite z and NaN when z is NaN or
+// infinite, so that a NaN argument reaches the result (an infinite z, from an
 // infinite state or one within a factor ~16 of overflow, then gives NaN
 // instead of 0 or 1); without it a NaN z gives a finite result, for callers
 // whose NaN z implies a NaN state component anyway.
 template <bool KEEP_NAN>
 __device__ __forceinline__ double logistic_k(double z) {
-    const double lo = KEEP_NAN ? __builtin_fma(0.0, z, -700.0) : -700.0;
-    const double hi = KEEP_NAN ? __builtin_fma(0.0, z, 700.0) : 700.0;
-    const double zc = __builtin_fmin(__builtin_fmax(z, lo), hi);
-    return M<double>::rcp_k(1.0 + M<double>::exp_k(zc));
+    const double zc = __builtin_fmin(__builtin_fmax(z, -700.0), 700.0);
+    const double s = M<double>::rcp_k(1.0 + M<double>::exp_k(zc));
+    return KEEP_NAN ? __builtin_fma(0.0, z, s) : s;
+}
+
+// 1/(1 + 2^t), the same in base 2 for arguments that already carry the
+// factor log2(e): t clamped to [-1000, 1000] (2^-1000 = 9.3e-302).
+template <bool KEEP_NAN>
+__device__ __forceinline__ double logistic2_k(double t) {
+    const double tc = __builtin_fmin(__builtin_fmax(t, -1000.0), 1000.0);
+    const double s = M<double>::rcp_k(1.0 + M<double>::exp2_k(tc));
+    return KEEP_NAN ? __builtin_fma(0.0, t, s) : s;
 }
 
 template <typename R> constexpr bool kHasKernels = std::is_same<R, double>::value;
@@ -108,14 +120,17 @@ template <typename R> struct Lorenz {
 // E' = -E + S_E(c1 E - c2 I + P), I' = -I + S_I(c3 E - c4 I + Q),
 // S(u) = 1/(1 + exp(-a (u - th)));  p = [c1, c2, c3, c4, aE, thE, aI, thI, P, Q].
 template <typename R> struct WilsonCowan {
-    // Fast single precision folds the gain into the sigmoid's argument: with
-    // g = -a*log2(e), (u - th)*g = fma(c1*g, E, fma(-c2*g, I, (P - th)*g)),
-    // three constants per population derived once per particle, so each
-    // S = 1/(1 + 2^z) costs two fma, exp2, add and rcp.  (The folded constants
+    // Fast single precision and double precision fold the gain into the
+    // sigmoid's argument: with g = -a*log2(e),
+    // (u - th)*g = fma(c1*g, E, fma(-c2*g, I, (P - th)*g)), three constants
+    // per population derived once per particle, so each S = 1/(1 + 2^t)
+    // costs two fma, exp2, add and rcp (in double precision the kernels of
+    // logistic2_k, which also clamp t and keep a NaN).  The folded constants
     // round the same number of times as the canonical order, with errors of
-    // the same size.)  Otherwise the canonical order below is kept.
-    static constexpr bool kFold = M<R>::kFast;
-    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1, FUSED_INC = kFold;
+    // the same size.  Single precision with the library functions keeps the
+    // canonical order below.
+    static constexpr bool kFold = M<R>::kFast || kHasKernels<R>;
+    static constexpr int D = 2, NP = 10, NQ = kFold ? 6 : 1, UNROLL = 1, FUSED_INC = M<R>::kFast;
     static __device__ __forceinline__ void derive(const R (&p)[NP], R (&q)[NQ]) {
         if constexpr (kFold) {
             const R gE = -p[4] * R(kLog2e), gI = -p[6] * R(kLog2e);
@@ -130,20 +145,18 @@ template <typename R> struct WilsonCowan {
         }
     }
     static __device__ __forceinline__ void sigmoids(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R& sE, R& sI) {
-        if constexpr (kFold) {
+        if constexpr (kHasKernels<R>) {
+            // a NaN per-particle P must reach the state through S_E
+            sE = logistic2_k<true>(M<R>::fma_(q[0], x[0], M<R>::fma_(q[1], x[1], q[2])));
+            sI = logistic2_k<true>(M<R>::fma_(q[3], x[0], M<R>::fma_(q[4], x[1], q[5])));
+        } else if constexpr (kFold) {
             sE = M<R>::rcp_(R(1) + M<R>::exp2_(M<R>::fma_(q[0], x[0], M<R>::fma_(q[1], x[1], q[2]))));
             sI = M<R>::rcp_(R(1) + M<R>::exp2_(M<R>::fma_(q[3], x[0], M<R>::fma_(q[4], x[1], q[5]))));
         } else {
             const R uE = M<R>::fma_(p[0], x[0], M<R>::fma_(-p[1], x[1], p[8]));
             const R uI = M<R>::fma_(p[2], x[0], M<R>::fma_(-p[3], x[1], p[9]));
-            if constexpr (kHasKernels<R>) {
-                // a NaN per-particle P must reach the state through S_E
-                sE = logistic_k<true>(-(p[4] * (uE - p[5])));
-                sI = logistic_k<true>(-(p[6] * (uI - p[7])));
-            } else {
-                sE = M<R>::rcp_(R(1) + M<R>::exp_(-(p[4] * (uE - p[5]))));
-                sI = M<R>::rcp_(R(1) + M<R>::exp_(-(p[6] * (uI - p[7]))));
-            }
+            sE = M<R>::rcp_(R(1) + M<R>::exp_(-(p[4] * (uE - p[5]))));
+            sI = M<R>::rcp_(R(1) + M<R>::exp_(-(p[6] * (uI - p[7]))));
         }
     }
     static __device__ __forceinline__ void f(const R (&p)[NP], const R (&q)[NQ], const R (&x)[D], R (&o)[D]) {
