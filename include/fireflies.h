@@ -426,6 +426,35 @@ ff_status ff_integrate_groups(const ff_group* groups, int32_t n_groups, int64_t 
 ff_status ff_autotune(const ff_group* groups, int32_t n_groups, int64_t nsteps, ff_tuning* out,
                       void* stream);
 
+/* Accuracy check of the double-precision elementary kernels the built-in
+ * Wilson-Cowan and Hodgkin-Huxley right-hand sides evaluate (the paper fixes
+ * no exponential or division; these are the library's own, Cody-Waite
+ * reductions and Chebyshev interpolants): y[i] = fn(x[i]) for i < n, with x
+ * and y device arrays of n doubles (caller-owned; y may equal x).  fn is one
+ * of ff_math; the argument ranges each kernel is valid for:
+ *   FF_MATH_EXP       e^x, |x| <= 708 (gradual underflow included)
+ *   FF_MATH_EXP2      2^x, |x| <= 2^31 (inf above 1024, 0 below -1075)
+ *   FF_MATH_EXPM1     e^x - 1, |x| <= 708
+ *   FF_MATH_RCP       1/x, 2^-1022 <= |x| <= 2^1022
+ *   FF_MATH_LOGISTIC  1/(1 + e^x) with x clamped to [-700, 700], any x; NaN
+ *                     for a NaN or infinite x
+ *   FF_MATH_LOGISTIC2 1/(1 + 2^x) with x clamped to [-1000, 1000], any x; NaN
+ *                     for a NaN or infinite x
+ *   FF_MATH_PSI       x/(e^x - 1) (1 at x = 0) with e^x - 1 taken at
+ *                     min(x, 700), for x >= -708
+ * Enqueues one launch on stream.  FF_E_INVALID for an unknown fn, n < 0, or
+ * x or y NULL with n > 0; n == 0 launches nothing. */
+enum {
+    FF_MATH_EXP = 0,
+    FF_MATH_EXP2 = 1,
+    FF_MATH_EXPM1 = 2,
+    FF_MATH_RCP = 3,
+    FF_MATH_LOGISTIC = 4,
+    FF_MATH_LOGISTIC2 = 5,
+    FF_MATH_PSI = 6
+};
+ff_status ff_math_eval(int32_t fn, const double* x, double* y, int64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

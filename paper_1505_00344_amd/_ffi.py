@@ -83,6 +83,7 @@ SIGNATURES = {
     "ff_groups_workspace_size": (_i32, [_i32, _c.POINTER(_sz)]),
     "ff_integrate_groups": (_i32, [_c.POINTER(Group), _i32, _i64, _c.POINTER(Tuning), _vp, _sz, _vp]),
     "ff_autotune": (_i32, [_c.POINTER(Group), _i32, _i64, _c.POINTER(Tuning), _vp]),
+    "ff_math_eval": (_i32, [_i32, _vp, _vp, _i64, _vp]),
 }
 
 _lib = None

@@ -410,3 +410,19 @@ def autotune(groups, nsteps: int, stream=None) -> Tuning:
     out = Tuning()
     call("ff_autotune", groups, len(groups), int(nsteps), ctypes.byref(out), _stream(stream))
     return out
+
+
+MATH = {"exp": 0, "exp2": 1, "expm1": 2, "rcp": 3, "logistic": 4, "logistic2": 5, "psi": 6}
+
+
+def math_eval(fn: str, x: torch.Tensor, *, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """ff_math_eval: the library's double-precision kernel ``fn`` (a key of
+    MATH) applied elementwise to the float64 GPU tensor ``x``."""
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    _check_out(out, "out", tuple(x.shape), (torch.float64,))
+    _check_gpu(x, x=x, out=out)
+    call("ff_math_eval", MATH[fn], x.data_ptr(), out.data_ptr(), x.numel(), _stream(stream))
+    return out

@@ -125,6 +125,17 @@ def test_noops_touch_no_device(L):
         assert L.ff_integrate(s.handle, ctypes.byref(b), dt, n, None, None) == 0
 
 
+def test_math_eval_validation_on_host(L):
+    # rejected before any launch, so no device is needed; n == 0 launches nothing
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ff_math_eval(7, fake, fake, 4, None) == 1
+    assert L.ff_math_eval(-1, fake, fake, 4, None) == 1
+    assert L.ff_math_eval(0, fake, fake, -1, None) == 1
+    assert L.ff_math_eval(0, None, fake, 4, None) == 1
+    assert L.ff_math_eval(6, fake, None, 4, None) == 1
+    assert L.ff_math_eval(0, None, None, 0, None) == 0
+
+
 def test_bad_tuning_rejected(L):
     from paper_1505_00344_amd import _ffi
     from paper_1505_00344_amd import api as A
