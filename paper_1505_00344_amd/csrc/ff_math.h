@@ -141,9 +141,10 @@ template <> struct M<double> {
 // hardware 2^x (v_exp_f32) with log2(e) folded into the argument's scale, and
 // reciprocals/divisions use v_rcp_f32 (each about 1 ulp); expm1 stays the
 // library function because psi(u) near u = 0 needs it.  FF_FAST_F32 = 0 uses
-// the library expf and correctly rounded division instead.  Double precision
-// uses the library exp/expm1 (or the kernels above, where a caller has checked
-// the arguments) and the Newton-refined reciprocal.
+// the library expf and correctly rounded division instead.  In double
+// precision the built-in right-hand sides use the kernels above on clamped
+// arguments, and the Newton-refined reciprocal with its fallback where the
+// divisor is a parameter (1/C).
 #ifndef FF_FAST_F32
 #define FF_FAST_F32 1
 #endif
