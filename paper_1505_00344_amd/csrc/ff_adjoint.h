@@ -32,23 +32,26 @@ inline AdjArgs make_adj_args(const AdjLaunch& A) {
     return a;
 }
 
-template <template <typename> class SysT, int T, bool LOWREG = false>
+// T: register-tape length; CAPTURE: keep the stage points too (single
+// precision with T32, double with T64 and CAPTURE64, where registers allow).
+template <template <typename> class SysT, int T, bool LOWREG = false, bool CAPTURE = false, int T64 = T,
+          bool CAPTURE64 = CAPTURE>
 hipError_t dispatch_adj(const AdjLaunch& A) {
     const int64_t grid = (A.f.n + kAdjBlock - 1) / kAdjBlock;
     if (grid <= 0) return hipSuccess;
     const AdjArgs a = make_adj_args(A);
     switch (A.f.prec) {
         case FF_FP64:
-            hipLaunchKernelGGL((k_adj<SysT<double>, double, false, T, LOWREG>), dim3((unsigned)grid), dim3(kAdjBlock), 0,
-                               A.f.stream, a);
+            hipLaunchKernelGGL((k_adj<SysT<double>, double, false, T64, LOWREG, CAPTURE64>), dim3((unsigned)grid),
+                               dim3(kAdjBlock), 0, A.f.stream, a);
             break;
         case FF_FP32:
-            hipLaunchKernelGGL((k_adj<SysT<float>, float, false, T, LOWREG>), dim3((unsigned)grid), dim3(kAdjBlock), 0,
-                               A.f.stream, a);
+            hipLaunchKernelGGL((k_adj<SysT<float>, float, false, T, LOWREG, CAPTURE>), dim3((unsigned)grid),
+                               dim3(kAdjBlock), 0, A.f.stream, a);
             break;
         case FF_FP32_KAHAN:
-            hipLaunchKernelGGL((k_adj<SysT<float>, float, true, T, LOWREG>), dim3((unsigned)grid), dim3(kAdjBlock), 0,
-                               A.f.stream, a);
+            hipLaunchKernelGGL((k_adj<SysT<float>, float, true, T, LOWREG, CAPTURE>), dim3((unsigned)grid),
+                               dim3(kAdjBlock), 0, A.f.stream, a);
             break;
         default: return hipErrorInvalidValue;
     }

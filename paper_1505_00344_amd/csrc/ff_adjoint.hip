@@ -22,10 +22,12 @@ namespace ff {
 
 // The 15-variable ring (and expression systems of more than four variables)
 // keep one step on the tape and recompute stage points (LOWREG); the small
-// systems keep eight.
-int adj_tape_len(const ff_system_s* sys) {
+// systems keep eight, Lorenz in double precision four (it also keeps every
+// tape state's stage points; the launcher in k_adj_lorenz.hip must agree).
+int adj_tape_len(const ff_system_s* sys, int prec) {
     if (sys->rhs == FF_RHS_HH_RING) return 1;
     if (sys->rhs == FF_RHS_EXPR) return sys->dim <= 4 ? 8 : 1;
+    if (sys->rhs == FF_RHS_LORENZ && prec == FF_FP64) return 4;
     return 8;
 }
 
@@ -42,7 +44,7 @@ AdjLayout adj_layout(const ff_system_s* sys, const ff_batch* b, int64_t nsteps, 
     AdjLayout L{};
     const size_t esz = prec_size(b->prec);
     const bool kahan = b->prec == FF_FP32_KAHAN;
-    const int64_t T = adj_tape_len(sys);
+    const int64_t T = adj_tape_len(sys, b->prec);
     L.nseg = nsteps > 0 ? (nsteps + K - 1) / K : 0;
     const int64_t seg = nsteps < K ? nsteps : K;
     L.nsub = seg > 0 ? (seg + T - 1) / T : 0;

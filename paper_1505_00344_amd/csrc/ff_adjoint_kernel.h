@@ -21,7 +21,9 @@
 //      so no scratch), then applies T reverse steps.
 // The replays run the same rk4_step code as the forward kernel, so every
 // recomputed state is bitwise the forward state.  Cost per step: two forward
-// steps (A and B), three right-hand sides for the stage points and four VJPs.
+// steps (A and B), three right-hand sides for the stage points and four VJPs;
+// with CAPTURE, B keeps the stage points it computes anyway (and computes
+// those of its last state), so the reverse steps evaluate no right-hand side.
 //
 // Device code only: the library instantiates it for its built-in systems and
 // hands the same text to hipRTC for systems given as expressions.
@@ -60,13 +62,20 @@ struct AdjArgs {
 // parked in LDS, in this thread's own column of `lds` (3 * D rows of
 // kAdjBlock entries, no sharing between threads, so no barrier), and each is
 // loaded back when its vector-Jacobian product needs it.
-template <class S, typename R, bool LOWREG>
+// With HAVE_YS the stage points come in `given` (kept by the replay that
+// produced x) instead of being recomputed.
+template <class S, typename R, bool LOWREG, bool HAVE_YS = false>
 __device__ __forceinline__ void vjp_step(const R (&p)[S::NP], const R (&q)[S::NQ], const R (&x)[S::D],
                                          R (&lam)[S::D], R (&gp)[S::NP], R h, R h2, R h6, R h3,
-                                         R* lds = nullptr) {
+                                         R* lds = nullptr, const R (*given)[S::D] = nullptr) {
     constexpr int D = S::D;
     R ys[3][D];  // y2, y3, y4 when !LOWREG
-    if constexpr (LOWREG) {
+    if constexpr (HAVE_YS) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int d = 0; d < D; ++d) ys[j][d] = given[j][d];
+    } else if constexpr (LOWREG) {
         R y[D], k[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) y[d] = x[d];
@@ -142,7 +151,10 @@ template <class S> struct AdjMinBlocks {
     static constexpr int value = 1;
 };
 
-template <class S, typename R, bool KAHAN, int T, bool LOWREG>
+// CAPTURE (register tape only): the replay of a sub-block also keeps the
+// stage points of every tape state, so that the reverse steps need no right-hand
+// side evaluations of their own (3 * T more values in registers).
+template <class S, typename R, bool KAHAN, int T, bool LOWREG, bool CAPTURE = false>
 __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjArgs a) {
     constexpr int D = S::D, NP = S::NP;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,6 +224,7 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
     for (int64_t b = nsub - 1; b >= 0; --b) {
         const int64_t len = (L - b * T) < T ? (L - b * T) : T;
         R tape[T][D];
+        R stg[CAPTURE ? T : 1][3][D];
         R xs[D], cs[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -219,17 +232,35 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
             cs[d] = (KAHAN && T > 1) ? subc[b * D * n + d * n + i] : R(0);
             tape[0][d] = xs[d];
         }
+        if constexpr (CAPTURE) {
 #pragma unroll
-        for (int t = 1; t < T; ++t) {
-            if (t < len) {
-                rk4_step<S, R, KAHAN>(p, qd, xs, cs, h, h2, h6);
+            for (int t = 0; t < T; ++t) {
+                if (t + 1 < len) {
+                    rk4_step<S, R, KAHAN, true>(p, qd, xs, cs, h, h2, h6, stg[t]);
 #pragma unroll
-                for (int d = 0; d < D; ++d) tape[t][d] = xs[d];
+                    for (int d = 0; d < D; ++d) tape[t + 1][d] = xs[d];
+                } else if (t + 1 == len) {
+                    rk4_step<S, R, KAHAN, true, false>(p, qd, xs, cs, h, h2, h6, stg[t]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 1; t < T; ++t) {
+                if (t < len) {
+                    rk4_step<S, R, KAHAN>(p, qd, xs, cs, h, h2, h6);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) tape[t][d] = xs[d];
+                }
             }
         }
 #pragma unroll
         for (int t = T - 1; t >= 0; --t) {
-            if (t < len) vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3, stage_lds);
+            if (t < len) {
+                if constexpr (CAPTURE)
+                    vjp_step<S, R, false, true>(p, qd, tape[t], lam, gp, h, h2, h6, h3, nullptr, stg[t]);
+                else
+                    vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3, stage_lds);
+            }
         }
     }
     if (act) {

@@ -53,7 +53,7 @@ struct AdjLaunch {
 };
 
 // Steps held in registers by the adjoint's innermost recompute (per system).
-int adj_tape_len(const ff_system_s* sys);
+int adj_tape_len(const ff_system_s* sys, int prec);
 
 // Per-system fused RK4 launchers (one translation unit each).
 hipError_t launch_rk4_linear(int dim, const RK4Launch& L);

@@ -44,27 +44,36 @@ struct ParamBlock {
     double v[kMaxParams];
 };
 
-template <class S, typename R, bool KAHAN>
+// With STAGES the stage points y2, y3, y4 of the step are also written to
+// ys[0..2] (the adjoint's replay keeps them for the reverse step); with
+// UPDATE false only they are computed and x, c are left unchanged.
+template <class S, typename R, bool KAHAN, bool STAGES = false, bool UPDATE = true>
 __device__ __forceinline__ void rk4_step(const R (&p)[S::NP], const R (&q)[S::NQ], R (&x)[S::D], R (&c)[S::D],
-                                         R h, R h2, R h6) {
+                                         R h, R h2, R h6, R (*ys)[S::D] = nullptr) {
     constexpr int D = S::D;
     R k1[D], k[D], y[D], acc[D];
     S::f(p, q, x, k1);
 #pragma unroll
-    for (int d = 0; d < D; ++d) y[d] = M<R>::fma_(h2, k1[d], x[d]);
+    for (int d = 0; d < D; ++d) {
+        y[d] = M<R>::fma_(h2, k1[d], x[d]);
+        if constexpr (STAGES) ys[0][d] = y[d];
+    }
     S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         y[d] = M<R>::fma_(h2, k[d], x[d]);
+        if constexpr (STAGES) ys[1][d] = y[d];
         acc[d] = k[d];
     }
     S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         y[d] = M<R>::fma_(h, k[d], x[d]);
+        if constexpr (STAGES) ys[2][d] = y[d];
         acc[d] = acc[d] + k[d];
         acc[d] = M<R>::fma_(R(2), acc[d], k1[d]);
     }
+    if constexpr (!UPDATE) return;
     S::f(p, q, y, k);
 #pragma unroll
     for (int d = 0; d < D; ++d) {

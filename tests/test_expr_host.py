@@ -126,12 +126,20 @@ def test_groups_refuse_expression_systems_and_adjoint_layout(A):
     g = A.make_groups([(s, b, 0.01)])
     assert L.ff_integrate_groups(g, 1, 10, None, None, 0, None) == _ffi.FF_E_UNSUPPORTED
     # the adjoint workspace of a small expression system is laid out like the
-    # built-in system of the same size (tape of eight steps)
+    # built-in system of the same size with a tape of eight steps (the
+    # built-in Lorenz keeps four in double precision: one more sub-checkpoint
+    # for a 10-step segment)
     builtin = A.System("lorenz", 3, [10.0, 28.0, 8 / 3])
     sz, sz2 = ctypes.c_size_t(), ctypes.c_size_t()
+    b32 = _ffi.Batch()
+    b32.prec, b32.state, b32.n, b32.ld = _ffi.FF_FP32, 4096, 10, 10
+    assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b32), 100, 10, ctypes.byref(sz)) == 0
+    assert L.ff_adjoint_workspace_size(builtin.handle, ctypes.byref(b32), 100, 10, ctypes.byref(sz2)) == 0
+    assert sz.value == sz2.value
     assert L.ff_adjoint_workspace_size(s.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz)) == 0
     assert L.ff_adjoint_workspace_size(builtin.handle, ctypes.byref(b), 100, 10, ctypes.byref(sz2)) == 0
-    assert sz.value == sz2.value
+    sub = 10 * 3 * 8    # one sub-checkpoint of 10 particles x 3 doubles
+    assert sz2.value - sz.value == (sub + 255) // 256 * 256
 
 
 def test_noop_calls_compile_nothing(A):
