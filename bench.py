@@ -61,10 +61,22 @@ HBM_PEAK_TBS = 8.0
 # (3 right-hand sides + 9 fma = 42), four products J(y_s)^T abar_s (12 with
 # sigma*a0 shared) with their parameter part (7) summed into g (3): 4 x 22 = 88,
 # the stage weights abar_{s-1} = fma(w, g_s, w' lam) (3 x 9 = 27), a = h/6 lam
-# (3) and lam += g (3): 68 + 163 = 231.  The kernel executes one more forward
-# step per step (the replay that fills its register tape), counted apart.
+# (3) and lam += g (3): 68 + 163 = 231.  The kernel also replays every
+# sub-block of its register tape (T states: 8 in single precision, 4 in
+# double), keeping the stage points it computes there, so per segment of K
+# steps it executes K - ceil(K/T) more forward steps and ceil(K/T) stage-point
+# sets in place of the K stage-point sets counted above; the difference is
+# counted apart (adj_replay_extra_flop).
 ADJ_FLOP_PER_STEP = {"fp32": 231, "fp32_kahan": 240, "fp64": 231}
-ADJ_EXTRA_REPLAY_FLOP = {"fp32": 68, "fp32_kahan": 77, "fp64": 68}
+ADJ_TAPE = {"fp32": 8, "fp32_kahan": 8, "fp64": 4}
+ADJ_STAGE_FLOP = 42
+
+
+def adj_replay_extra_flop(prec, K):
+    """Executed FLOP per adjoint step beyond ADJ_FLOP_PER_STEP (Lorenz)."""
+    nsub = -(-K // ADJ_TAPE[prec])
+    fwd = FLOP_PER_STEP["lorenz"][prec]
+    return ((K - nsub) * fwd + nsub * ADJ_STAGE_FLOP) / K - ADJ_STAGE_FLOP
 # Sources that define the dominant kernel and its launch shape (ff_api.hip
 # holds the default tuning); the HBM traffic measured with rocprofv3 counters
 # is reported only while their hash matches the one recorded next to the
@@ -335,7 +347,7 @@ def lorenz_adjoint(A, torch, w, sysobj, st0, pp, prec):
     bwd = _time_stream(torch, back, reps=3)
     rate = w.n * adj["nsteps"] / (bwd * 1e-3)
     tf = rate * ADJ_FLOP_PER_STEP[prec] / 1e12
-    tf_exec = rate * (ADJ_FLOP_PER_STEP[prec] + ADJ_EXTRA_REPLAY_FLOP[prec]) / 1e12
+    tf_exec = rate * (ADJ_FLOP_PER_STEP[prec] + adj_replay_extra_flop(prec, adj["K"])) / 1e12
     return {"reverse_ms": bwd, "forward_ckpt_ms": fwd,
             "adjoint_steps_per_s": rate,
             "adjoint_steps_per_s_incl_forward": w.n * adj["nsteps"] / ((bwd + fwd) * 1e-3),
