@@ -1,6 +1,6 @@
 """Accuracy of the library's double-precision elementary kernels on the device
 (ff_math_eval): the exp, exp2 and expm1 kernels (Cody-Waite reduction and
-Chebyshev interpolants), the Newton-refined reciprocal, the clamped
+Chebyshev interpolants), the refined reciprocal, the clamped
 logistics of the Wilson-Cowan and Hodgkin-Huxley right-hand sides and the
 HH rate function psi(u) = u/(e^u - 1) (Section 3's rates; the paper fixes no
 exponential of its own).  The reference is the same function in 80-bit long
