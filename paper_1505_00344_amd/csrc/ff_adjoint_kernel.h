@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
     for (int64_t b = nsub - 1; b >= 0; --b) {
         const int64_t len = (L - b * T) < T ? (L - b * T) : T;
         R tape[T][D];
-        R stg[CAPTURE ? T : 1][3][D];
+        R stages[CAPTURE ? T : 1][3][D];  // y2, y3, y4 of every tape state (CAPTURE)
         R xs[D], cs[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -236,11 +236,11 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 if (t + 1 < len) {
-                    rk4_step<S, R, KAHAN, true>(p, qd, xs, cs, h, h2, h6, stg[t]);
+                    rk4_step<S, R, KAHAN, true>(p, qd, xs, cs, h, h2, h6, stages[t]);
 #pragma unroll
                     for (int d = 0; d < D; ++d) tape[t + 1][d] = xs[d];
-                } else if (t + 1 == len) {
-                    rk4_step<S, R, KAHAN, true, false>(p, qd, xs, cs, h, h2, h6, stg[t]);
+                } else if (t + 1 == len) {  // the last state: its stage points only
+                    rk4_step<S, R, KAHAN, true, false>(p, qd, xs, cs, h, h2, h6, stages[t]);
                 }
             }
         } else {
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(kAdjBlock, AdjMinBlocks<S>::value) k_adj(AdjAr
         for (int t = T - 1; t >= 0; --t) {
             if (t < len) {
                 if constexpr (CAPTURE)
-                    vjp_step<S, R, false, true>(p, qd, tape[t], lam, gp, h, h2, h6, h3, nullptr, stg[t]);
+                    vjp_step<S, R, false, true>(p, qd, tape[t], lam, gp, h, h2, h6, h3, nullptr, stages[t]);
                 else
                     vjp_step<S, R, LOWREG>(p, qd, tape[t], lam, gp, h, h2, h6, h3, stage_lds);
             }
